@@ -1,0 +1,169 @@
+/*
+ * cpht: compact parallel hash tables for AMD Instinct MI355X (gfx950).
+ *
+ * Lockless batched insert and find on compact (quotiented) bucketed hash
+ * tables, after "Compact Parallel Hash Tables on the GPU" (Hegeman, Woltgens,
+ * Wijs, Laarman; arXiv 2406.09255):
+ *
+ *   - compact bucketed cuckoo hashing (Sec. 2.2, Sec. 4.4 Alg. 4): a static
+ *     table, bulk-built from distinct keys and then queried;
+ *   - compact two-level iceberg hashing (Sec. 2.3, Sec. 3 Alg. 1, Sec. 4.2
+ *     Alg. 2/3): a dynamic table with a concurrent find-or-put returning
+ *     PUT / FOUND / FULL, and lookups that may run beside it.
+ *
+ * Quotienting (Sec. 2.4): a seeded bijection pi_i on w-bit keys; the high
+ * log2(#buckets) bits of pi_i(k) select the bucket (the address a_i(k)), and
+ * only the remaining bits r_i(k) are stored in the slot.
+ *
+ * Conventions for every call below
+ *   - Keys are device arrays of uint32 words when key_bits <= 32, uint64
+ *     words otherwise; a key must be < 2^key_bits (larger values are
+ *     undefined behaviour, not checked).
+ *   - Result arrays are device arrays of one byte per key.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Batch
+ *     calls are asynchronous and stream-ordered: they return once the work is
+ *     queued.  The caller keeps key and result buffers alive until the
+ *     stream has finished with them.  Calls that return data to the host
+ *     (cpht_count, cpht_export) synchronise.
+ *   - Argument and configuration errors are reported synchronously and
+ *     nothing is launched.  A kernel launch failure returns CPHT_E_DEVICE; a
+ *     fault inside a kernel surfaces at the next synchronising call.
+ *   - The library owns table memory (device memory of the device current at
+ *     cpht_create).  Batch calls allocate nothing.
+ *   - n = 0 is valid for every batch call and launches nothing.
+ */
+#ifndef CPHT_H
+#define CPHT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cpht_table* cpht_table_t;
+
+typedef enum {
+    CPHT_OK = 0,
+    CPHT_E_ARG = 1,          /* null pointer, bad size or value */
+    CPHT_E_NOMEM = 2,        /* device allocation failed */
+    CPHT_E_UNSUPPORTED = 3,  /* configuration not representable (e.g. remainder + tag + 1 > slot bits) */
+    CPHT_E_KEYRANGE = 4,     /* reserved */
+    CPHT_E_DEVICE = 5,       /* HIP runtime error */
+    CPHT_E_BUSY = 6,         /* reserved */
+    CPHT_E_STATE = 7         /* operation not valid for this table (e.g. mixed batch on cuckoo) */
+} cpht_status_t;
+
+/* Insert outcomes (one byte per key).  0 = key not processed. */
+enum { CPHT_PUT = 1, CPHT_FOUND = 2, CPHT_FULL = 3 };
+/* Opcodes of a mixed batch. */
+enum { CPHT_OP_FIND = 0, CPHT_OP_INSERT = 1 };
+/* Schemes. */
+enum { CPHT_CUCKOO = 0, CPHT_ICEBERG = 1 };
+
+typedef struct {
+    uint32_t scheme;       /* CPHT_CUCKOO or CPHT_ICEBERG */
+    uint32_t key_bits;     /* w, 1..64 */
+    uint32_t log2_slots0;  /* cuckoo: log2 of all slots; iceberg: primary level */
+    uint32_t log2_slots1;  /* iceberg: secondary ("backyard") level; cuckoo: ignored */
+    uint32_t bucket0;      /* slots per bucket (primary); power of two */
+    uint32_t bucket1;      /* iceberg: slots per secondary bucket, must be bucket0/2 */
+    uint32_t slot_bits0;   /* 16 (iceberg only), 32 or 64 */
+    uint32_t slot_bits1;   /* iceberg secondary: 16, 32 or 64 */
+    uint32_t n_hash;       /* cuckoo: H, 2 or 3 */
+    uint32_t max_chain;    /* cuckoo: eviction rounds C before FULL */
+    uint32_t subtile;      /* lanes cooperating on one bucket; 0 = default for the bucket size */
+    uint32_t compact;      /* 1 = store remainders (quotienting); 0 = store the full pi_i(k) */
+    uint64_t seed;         /* seed of the permutations pi_0, pi_1, pi_2 */
+} cpht_config_t;
+
+/* Defaults: cuckoo H=2, C=256, 2^20 slots in buckets of 32 x 32-bit slots;
+ * iceberg 2^20 + 2^17 slots, 32 x 16-bit primary and 16 x 32-bit secondary
+ * slots (the shape of the paper's experiments, Sec. 5.1), key_bits 32,
+ * compact, seed 1. */
+void cpht_config_default(uint32_t scheme, cpht_config_t* cfg);
+
+/* Create an empty table (synchronous: allocates and zeroes device memory).
+ * Level x holds 2^log2_slots_x slots in buckets of bucket_x slots; each
+ * bucket is bucket_x*slot_bits_x/8 contiguous bytes.  The stored remainder
+ * has key_bits - log2(#buckets) bits (key_bits bits if compact = 0); with
+ * its tag (cuckoo: ceil(log2 H) bits; iceberg secondary: 1 bit) and one
+ * occupancy bit it must fit the slot, else CPHT_E_UNSUPPORTED. */
+cpht_status_t cpht_create(const cpht_config_t* cfg, cpht_table_t* out);
+
+/* Free the table's device memory.  Pending work using it must have finished. */
+cpht_status_t cpht_destroy(cpht_table_t t);
+
+/* The resolved configuration (subtile filled in). */
+cpht_status_t cpht_get_config(cpht_table_t t, cpht_config_t* cfg);
+
+/* Empty the table and re-derive the permutations from `seed` (stream-ordered;
+ * uses a fill kernel, no memset node). */
+cpht_status_t cpht_clear(cpht_table_t t, uint64_t seed, void* stream);
+
+/* Insert a batch.
+ *   Iceberg: find-or-put of every key (Sec. 3 Alg. 1, cooperative form
+ *   Alg. 2, batch form Alg. 3).  d_out[i] = CPHT_PUT if this call stored
+ *   keys[i], CPHT_FOUND if the key was already present (stored earlier or by
+ *   another operation of the batch), CPHT_FULL if its primary bucket and both
+ *   secondary buckets are full without it.  Duplicates are allowed; at most
+ *   one operation per key returns PUT.  May run concurrently with cpht_find
+ *   and other cpht_insert calls on the same table.
+ *   Cuckoo: compact cuckoo put (Sec. 4.4 Alg. 4).  Keys must be distinct and
+ *   absent from the table, and no find may run concurrently (the table is
+ *   static, Sec. 4.4).  d_out[i] = CPHT_PUT, or CPHT_FULL when an eviction
+ *   chain exceeded max_chain; the key dropped then is the one being carried,
+ *   which need not be keys[i]. */
+cpht_status_t cpht_insert(cpht_table_t t, const void* d_keys, uint64_t n, uint8_t* d_out, void* stream);
+
+/* Same as cpht_insert; the name used for the static build of a cuckoo table. */
+cpht_status_t cpht_bulk_build(cpht_table_t t, const void* d_keys, uint64_t n, uint8_t* d_out, void* stream);
+
+/* Lookup of a batch: d_found[i] = 1 if keys[i] is in the table, else 0.
+ * Cuckoo: buckets a_0(k), a_1(k), ... in order, stopping at the first bucket
+ * that is not full (Sec. 4.4 "Lookup").  Iceberg: the primary bucket, and
+ * both secondary buckets only when the primary is full (Sec. 2.3 "Lookup"). */
+cpht_status_t cpht_find(cpht_table_t t, const void* d_keys, uint64_t n, uint8_t* d_found, void* stream);
+
+/* Iceberg only: one batch of finds (d_ops[i] = CPHT_OP_FIND, answer 0/1) and
+ * find-or-puts (CPHT_OP_INSERT, answer PUT/FOUND/FULL) executed concurrently
+ * (dynamic operation, Sec. 1 and Sec. 3).  A find of a key that another
+ * operation of the same batch inserts may answer either way. */
+cpht_status_t cpht_mixed(cpht_table_t t, const void* d_keys, const uint8_t* d_ops, uint64_t n, uint8_t* d_out,
+                         void* stream);
+
+/* Occupied slots and total slots over all levels (fill factor = occupied /
+ * capacity, Sec. 2.1).  Synchronises `stream`. */
+cpht_status_t cpht_count(cpht_table_t t, uint64_t* occupied, uint64_t* capacity, void* stream);
+
+/* Size in bytes of level `level` (0, or 1 for the iceberg secondary level). */
+cpht_status_t cpht_level_bytes(cpht_table_t t, uint32_t level, uint64_t* bytes);
+
+/* Device pointer to level `level` (for callers that copy it themselves). */
+cpht_status_t cpht_level_ptr(cpht_table_t t, uint32_t level, void** d_ptr);
+
+/* Copy level `level` to host memory (synchronous).  Raw layout: bucket b,
+ * slot q at byte offset (b*bucket + q)*slot_bits/8, little endian; a slot is 0
+ * (EMPTY) or (1 << (slot_bits-1)) | tag << p | payload, where p is the
+ * payload width (key_bits - log2(#buckets), or key_bits if not compact). */
+cpht_status_t cpht_export(cpht_table_t t, uint32_t level, void* h_dst, uint64_t bytes);
+
+/* The quotienting split of Sec. 2.4 as the table applies it: for permutation
+ * `perm_index` (cuckoo: hash index j < H; iceberg: 0 = primary, 1 and 2 =
+ * the two secondary buckets), d_addr[i] = a(keys[i]) and d_stored[i] = the
+ * slot value the table stores for keys[i] there (with its tag). */
+cpht_status_t cpht_split(cpht_table_t t, uint32_t perm_index, const void* d_keys, uint64_t n, uint64_t* d_addr,
+                         uint64_t* d_stored, void* stream);
+
+/* Compiled kernel variants, for tuners: entry i of scheme `scheme` as
+ * (key64, slot_bits0, slot_bits1, bucket0, bucket1, subtile).  Returns the
+ * number of variants; fills *info (6 values) when info != NULL and i is valid. */
+int cpht_variant_info(uint32_t scheme, int i, uint32_t* info);
+
+const char* cpht_status_str(cpht_status_t s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPHT_H */

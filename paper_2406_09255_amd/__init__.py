@@ -1,0 +1,257 @@
+"""Compact parallel hash tables on AMD MI355X (gfx950): Python binding.
+
+A thin ctypes layer over ``libcpht.so`` (the C-ABI declared in
+``include/cpht.h``).  It only marshals arguments: torch tensors supply device
+buffers and the current HIP stream; every step of insert, find, count and the
+key split runs in the library's own HIP kernels.  There is no fallback: if the
+library is missing or a call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcpht.so")
+
+CUCKOO, ICEBERG = 0, 1
+PUT, FOUND, FULL = 1, 2, 3
+OP_FIND, OP_INSERT = 0, 1
+
+_STATUS = {
+    0: "ok", 1: "invalid argument", 2: "out of device memory", 3: "unsupported configuration",
+    4: "key out of range", 5: "device error", 6: "busy", 7: "operation not valid for this table",
+}
+
+
+class CphtError(RuntimeError):
+    def __init__(self, code: int, call: str):
+        super().__init__(f"{call}: {_STATUS.get(code, code)} (status {code})")
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    """Mirror of cpht_config_t."""
+
+    _fields_ = [
+        ("scheme", ctypes.c_uint32),
+        ("key_bits", ctypes.c_uint32),
+        ("log2_slots0", ctypes.c_uint32),
+        ("log2_slots1", ctypes.c_uint32),
+        ("bucket0", ctypes.c_uint32),
+        ("bucket1", ctypes.c_uint32),
+        ("slot_bits0", ctypes.c_uint32),
+        ("slot_bits1", ctypes.c_uint32),
+        ("n_hash", ctypes.c_uint32),
+        ("max_chain", ctypes.c_uint32),
+        ("subtile", ctypes.c_uint32),
+        ("compact", ctypes.c_uint32),
+        ("seed", ctypes.c_uint64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+# Every symbol include/cpht.h declares, with (restype, argtypes).
+_VP, _U32, _U64, _I32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+_SIGNATURES = {
+    "cpht_config_default": (None, [_U32, ctypes.POINTER(Config)]),
+    "cpht_create": (_I32, [ctypes.POINTER(Config), ctypes.POINTER(_VP)]),
+    "cpht_destroy": (_I32, [_VP]),
+    "cpht_get_config": (_I32, [_VP, ctypes.POINTER(Config)]),
+    "cpht_clear": (_I32, [_VP, _U64, _VP]),
+    "cpht_insert": (_I32, [_VP, _VP, _U64, _VP, _VP]),
+    "cpht_bulk_build": (_I32, [_VP, _VP, _U64, _VP, _VP]),
+    "cpht_find": (_I32, [_VP, _VP, _U64, _VP, _VP]),
+    "cpht_mixed": (_I32, [_VP, _VP, _VP, _U64, _VP, _VP]),
+    "cpht_count": (_I32, [_VP, ctypes.POINTER(_U64), ctypes.POINTER(_U64), _VP]),
+    "cpht_level_bytes": (_I32, [_VP, _U32, ctypes.POINTER(_U64)]),
+    "cpht_level_ptr": (_I32, [_VP, _U32, ctypes.POINTER(_VP)]),
+    "cpht_export": (_I32, [_VP, _U32, _VP, _U64]),
+    "cpht_split": (_I32, [_VP, _U32, _VP, _U64, _VP, _VP, _VP]),
+    "cpht_variant_info": (_I32, [_U32, _I32, ctypes.POINTER(_U32)]),
+    "cpht_status_str": (ctypes.c_char_p, [_I32]),
+}
+
+
+def lib():
+    """Load libcpht.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2406_09255_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code: int, call: str):
+    if code != 0:
+        raise CphtError(code, call)
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+
+
+def _dev_ptr(t: torch.Tensor, name: str) -> int:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def default_config(scheme: int) -> Config:
+    c = Config()
+    lib().cpht_config_default(scheme, ctypes.byref(c))
+    return c
+
+
+def variants(scheme: int) -> list[dict]:
+    """Compiled kernel variants of a scheme."""
+    n = lib().cpht_variant_info(scheme, -1, None)
+    out = []
+    buf = (_U32 * 6)()
+    for i in range(n):
+        lib().cpht_variant_info(scheme, i, buf)
+        out.append(dict(zip(("key64", "slot_bits0", "slot_bits1", "bucket0", "bucket1", "subtile"), list(buf))))
+    return out
+
+
+class Table:
+    """One compact hash table resident in device memory (cpht_table_t)."""
+
+    def __init__(self, config: Config | None = None, **fields):
+        scheme = fields.get("scheme", config.scheme if config is not None else CUCKOO)
+        cfg = Config()
+        if config is not None:
+            ctypes.memmove(ctypes.byref(cfg), ctypes.byref(config), ctypes.sizeof(Config))
+        else:
+            lib().cpht_config_default(scheme, ctypes.byref(cfg))
+        for k, v in fields.items():
+            setattr(cfg, k, int(v))
+        h = _VP()
+        _check(lib().cpht_create(ctypes.byref(cfg), ctypes.byref(h)), "cpht_create")
+        self._h = h
+        self.config = Config()
+        _check(lib().cpht_get_config(self._h, ctypes.byref(self.config)), "cpht_get_config")
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cpht_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- properties ---------------------------------------------------------
+    @property
+    def key_dtype(self) -> torch.dtype:
+        return torch.int32 if self.config.key_bits <= 32 else torch.int64
+
+    @property
+    def nlevels(self) -> int:
+        return 2 if self.config.scheme == ICEBERG else 1
+
+    def _keys(self, keys: torch.Tensor) -> int:
+        if keys.dtype != self.key_dtype:
+            raise ValueError(f"keys must be {self.key_dtype} words for key_bits={self.config.key_bits}")
+        return _dev_ptr(keys, "keys")
+
+    def _out(self, out: torch.Tensor | None, n: int, like: torch.Tensor) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(n, dtype=torch.uint8, device=like.device)
+        if out.dtype != torch.uint8 or out.numel() < n:
+            raise ValueError("out must be a uint8 device tensor with one byte per key")
+        return out
+
+    # -- batch operations (asynchronous on the stream) ----------------------
+    def clear(self, seed: int | None = None, stream=None):
+        s = self.config.seed if seed is None else seed
+        _check(lib().cpht_clear(self._h, s & (2**64 - 1), _stream(stream)), "cpht_clear")
+        self.config.seed = s & (2**64 - 1)
+
+    def insert(self, keys: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        n = keys.numel()
+        out = self._out(out, n, keys)
+        _check(lib().cpht_insert(self._h, self._keys(keys), n, _dev_ptr(out, "out"), _stream(stream)),
+               "cpht_insert")
+        return out
+
+    def bulk_build(self, keys: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        n = keys.numel()
+        out = self._out(out, n, keys)
+        _check(lib().cpht_bulk_build(self._h, self._keys(keys), n, _dev_ptr(out, "out"), _stream(stream)),
+               "cpht_bulk_build")
+        return out
+
+    def find(self, keys: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        n = keys.numel()
+        out = self._out(out, n, keys)
+        _check(lib().cpht_find(self._h, self._keys(keys), n, _dev_ptr(out, "out"), _stream(stream)),
+               "cpht_find")
+        return out
+
+    def mixed(self, keys: torch.Tensor, ops: torch.Tensor, out: torch.Tensor | None = None,
+              stream=None) -> torch.Tensor:
+        n = keys.numel()
+        if ops.dtype != torch.uint8 or ops.numel() != n:
+            raise ValueError("ops must be a uint8 tensor with one opcode per key")
+        out = self._out(out, n, keys)
+        _check(lib().cpht_mixed(self._h, self._keys(keys), _dev_ptr(ops, "ops"), n, _dev_ptr(out, "out"),
+                                _stream(stream)), "cpht_mixed")
+        return out
+
+    def split(self, perm_index: int, keys: torch.Tensor, stream=None):
+        n = keys.numel()
+        addr = torch.empty(n, dtype=torch.int64, device=keys.device)
+        stored = torch.empty(n, dtype=torch.int64, device=keys.device)
+        _check(lib().cpht_split(self._h, perm_index, self._keys(keys), n, _dev_ptr(addr, "addr"),
+                                _dev_ptr(stored, "stored"), _stream(stream)), "cpht_split")
+        return addr, stored
+
+    # -- synchronous queries ------------------------------------------------
+    def count(self, stream=None) -> tuple[int, int]:
+        occ, cap = _U64(0), _U64(0)
+        _check(lib().cpht_count(self._h, ctypes.byref(occ), ctypes.byref(cap), _stream(stream)), "cpht_count")
+        return occ.value, cap.value
+
+    def fill_factor(self, stream=None) -> float:
+        occ, cap = self.count(stream)
+        return occ / cap
+
+    def level_bytes(self, level: int) -> int:
+        b = _U64(0)
+        _check(lib().cpht_level_bytes(self._h, level, ctypes.byref(b)), "cpht_level_bytes")
+        return b.value
+
+    def export(self, level: int):
+        """Raw slot image of a level in host memory (numpy uint8)."""
+        import numpy as np  # host staging buffer only
+
+        nbytes = self.level_bytes(level)
+        buf = np.empty(nbytes, dtype=np.uint8)
+        _check(lib().cpht_export(self._h, level, buf.ctypes.data_as(_VP), nbytes), "cpht_export")
+        return buf

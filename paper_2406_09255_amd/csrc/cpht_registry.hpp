@@ -1,0 +1,51 @@
+// Table of compiled kernel variants.  Sizes that shape registers (slot bits,
+// bucket slots, sub-tile width) are template parameters; the host library
+// picks the variant matching a table's configuration.
+#pragma once
+#include "cpht_device.hpp"
+
+namespace cpht {
+
+typedef void (*launch_fn)(const TableK&, const BatchK&, hipStream_t);
+
+struct IceVariant {
+  int key64;           // 1: 64-bit key words
+  int S0, S1, B0, B1;  // slot bits and bucket slots per level
+  int G;               // sub-tile lanes
+  launch_fn find, insert, mixed;
+};
+
+struct CkVariant {
+  int key64;
+  int S, B, G;
+  launch_fn put, find;
+};
+
+// Iceberg variants: (S0, S1, B0, G) with B1 = B0 / 2.  The first entry for a
+// given (S0, S1, B0) is the default sub-tile width: one 16-byte load per lane
+// on the primary bucket where the bucket allows it.
+#define CPHT_ICE_LIST(X) \
+  X(16, 16, 8, 2)  X(16, 32, 8, 2)  X(32, 32, 8, 2)  X(64, 64, 8, 4)  \
+  X(16, 16, 16, 2) X(16, 32, 16, 2) X(32, 32, 16, 4) X(64, 64, 16, 8) \
+  X(16, 16, 32, 4) X(16, 32, 32, 4) X(32, 32, 32, 8) X(64, 64, 32, 16) \
+  X(16, 16, 64, 8) X(16, 32, 64, 8) X(32, 32, 64, 16) X(64, 64, 64, 32) \
+  X(16, 16, 32, 8) X(16, 32, 32, 8) X(32, 32, 32, 4) X(32, 32, 32, 16) X(64, 64, 32, 8) \
+  X(16, 32, 64, 16) X(16, 32, 16, 4)
+
+// Cuckoo variants: (S, B, G); first entry per (S, B) is the default.
+#define CPHT_CK_LIST(X) \
+  X(32, 8, 2) X(32, 16, 4) X(32, 32, 8) X(64, 8, 4) X(64, 16, 8) X(64, 32, 16) \
+  X(32, 32, 4) X(32, 32, 16) X(64, 32, 8) X(32, 16, 2) X(32, 16, 8)
+
+const IceVariant* ice_variants_u32(int* n);
+const IceVariant* ice_variants_u64(int* n);
+const CkVariant* ck_variants_u32(int* n);
+const CkVariant* ck_variants_u64(int* n);
+
+template <class Kern>
+inline void launch_grid(Kern k, const TableK& T, const BatchK& B, hipStream_t s) {
+  const uint64_t blocks = (B.n + 255) / 256;
+  hipLaunchKernelGGL(k, dim3((uint32_t)blocks), dim3(256), 0, s, T, B);
+}
+
+}  // namespace cpht

@@ -1,0 +1,19 @@
+// Cuckoo kernel instantiations for u64 key words.
+#include "cpht_cuckoo.hpp"
+#include "cpht_registry.hpp"
+
+namespace cpht {
+namespace {
+template <int S, int B, int G, bool PUT>
+void launch(const TableK& T, const BatchK& Bt, hipStream_t s) {
+  launch_grid(cuckoo_kernel<uint64_t, S, B, G, PUT>, T, Bt, s);
+}
+#define CPHT_CK_ENTRY(S, B, G) {1, S, B, G, &launch<S, B, G, true>, &launch<S, B, G, false>},
+const CkVariant kList[] = {CPHT_CK_LIST(CPHT_CK_ENTRY)};
+}  // namespace
+
+const CkVariant* ck_variants_u64(int* n) {
+  *n = (int)(sizeof(kList) / sizeof(kList[0]));
+  return kList;
+}
+}  // namespace cpht

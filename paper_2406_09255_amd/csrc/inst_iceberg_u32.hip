@@ -1,0 +1,21 @@
+// Iceberg kernel instantiations for u32 key words.
+#include "cpht_iceberg.hpp"
+#include "cpht_registry.hpp"
+
+namespace cpht {
+namespace {
+template <int S0, int S1, int B0, int B1, int G, int MODE>
+void launch(const TableK& T, const BatchK& B, hipStream_t s) {
+  launch_grid(iceberg_kernel<uint32_t, S0, S1, B0, B1, G, MODE>, T, B, s);
+}
+#define CPHT_ICE_ENTRY(S0, S1, B0, G) \
+  {0, S0, S1, B0, B0 / 2, G, &launch<S0, S1, B0, B0 / 2, G, MODE_FIND>, \
+   &launch<S0, S1, B0, B0 / 2, G, MODE_INSERT>, &launch<S0, S1, B0, B0 / 2, G, MODE_MIXED>},
+const IceVariant kList[] = {CPHT_ICE_LIST(CPHT_ICE_ENTRY)};
+}  // namespace
+
+const IceVariant* ice_variants_u32(int* n) {
+  *n = (int)(sizeof(kList) / sizeof(kList[0]));
+  return kList;
+}
+}  // namespace cpht
