@@ -1,0 +1,307 @@
+"""Benchmark: static bulk build then finds on a compact cuckoo table at GPU scale.
+
+Workload (one GPU): compact bucketed cuckoo hashing, H = 2 hash functions,
+2^27 slots in 2^22 buckets of 32 x 32-bit slots (128-byte buckets), 37-bit
+keys held in uint64 words.  One step = empty the table with a new permutation
+seed, bulk-insert 0.9 * 2^27 distinct keys (load 0.9), then 2^26 finds with
+50 % hits and 50 % misses.  The same step is also timed on the non-compact
+("plain") table: the same kernels with 64-bit slots that store all 37 bits of
+pi_j(k) (256-byte buckets).  Keys are synthetic, seeded, and already resident
+in device memory when the timed region starts.
+
+Prints one JSON line.  Extra fields: per-kernel Mops/s and p50/p99 batch
+latency for insert and find, compact vs plain, a load sweep, the roofline of
+the dominant kernel, and the sequential CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mops/s insert & find at load 0.9, compact vs plain; p50/p99 batch latency"
+W_KEY = 37
+LOG2_SLOTS = 27
+BUCKET = 32
+LOAD = 0.9
+N_FIND = 1 << 26
+KEY_SEED = 0xC2C2C2C2
+Q_SEED = 0x51515151
+HBM_PEAK_GBS = 8000.0
+LINE = 128
+
+# Bucket reads per operation counted by the sequential oracle model
+# (oracle/lines_per_op.py at 2^22 slots, buckets of 32 slots, 50 % hit finds):
+# cuckoo put rounds (one bucket read and one bucket write each) and find probes.
+ROUNDS_PER_PUT = {0.5: 1.00002, 0.7: 1.00252, 0.8: 1.01291, 0.9: 1.05175, 0.95: 1.11011}
+PROBES_PER_FIND = {0.5: 1.00014, 0.7: 1.01809, 0.8: 1.07518, 0.9: 1.22454, 0.95: 1.36303}
+KEY_BYTES = 8
+RESULT_BYTES = 1
+
+
+def put_bytes(load: float, bucket_lines: int) -> float:
+    """Algorithmic bytes of one put: each round reads a bucket and writes one line."""
+    return ROUNDS_PER_PUT[load] * (bucket_lines + 1) * LINE + KEY_BYTES + RESULT_BYTES
+
+
+def find_bytes(load: float, bucket_lines: int) -> float:
+    return PROBES_PER_FIND[load] * bucket_lines * LINE + KEY_BYTES + RESULT_BYTES
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = min(len(xs) - 1, max(0, int(round(q / 100.0 * (len(xs) - 1)))))
+    return xs[k]
+
+
+class Runner:
+    """Times build + find steps on one table with events on the launch stream."""
+
+    def __init__(self, torch, cpht, table, keys, queries, n_ins):
+        self.torch, self.cpht, self.t = torch, cpht, table
+        self.keys, self.queries, self.n_ins = keys, queries, n_ins
+        self.out = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
+        self.found = torch.empty(queries.numel(), dtype=torch.uint8, device=keys.device)
+        self.ev = []
+
+    def step(self, seed: int, n_ins: int | None = None, record: bool = True):
+        torch = self.torch
+        n = self.n_ins if n_ins is None else n_ins
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        self.t.clear(seed)
+        e[0].record()
+        self.t.bulk_build(self.keys[:n], self.out)
+        e[1].record()
+        self.t.find(self.queries, self.found)
+        e[2].record()
+        if record:
+            self.ev.append(e)
+
+    def times_ms(self):
+        self.torch.cuda.synchronize()
+        ins = [a.elapsed_time(b) for a, b, _ in self.ev]
+        fnd = [b.elapsed_time(c) for _, b, c in self.ev]
+        self.ev = []
+        return ins, fnd
+
+
+def cpu_baseline(log2_slots: int = 25):
+    """The sequential oracle on the host: same bucket shape, load and find mix,
+    at 2^log2_slots slots (a bounded sample of the workload)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+
+    n = int(LOAD * (1 << log2_slots))
+    nq = 1 << (log2_slots - 1)
+    keys = synth.distinct_keys(W_KEY, KEY_SEED, 0, n).numpy().astype(np.uint64)
+    q = synth.find_queries(W_KEY, KEY_SEED, n, nq, 0.5, Q_SEED).numpy().astype(np.uint64)
+    t = oracle.Table(oracle.CUCKOO, W_KEY, log2_slots, BUCKET, 32, seed=1)
+    t0 = time.perf_counter()
+    out = t.insert(keys)
+    t1 = time.perf_counter()
+    f = t.find(q)
+    t2 = time.perf_counter()
+    assert (out == oracle.PUT).all()
+    del torch
+    return {
+        "value": round((n + nq) / (t2 - t0) / 1e6, 3),
+        "unit": "Mops/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"sequential oracle, compact cuckoo 2^{log2_slots} slots (1/{1 << (LOG2_SLOTS - log2_slots)} "
+                   f"of the workload's slots, same 32 x 32-bit buckets), build to load {LOAD} ({n} keys) "
+                   f"then {nq} finds at 50% hit, one host thread"),
+        "insert_mops": round(n / (t1 - t0) / 1e6, 3),
+        "find_mops": round(nq / (t2 - t1) / 1e6, 3),
+        "seconds": round(t2 - t0, 2),
+        "hit_fraction": round(float(f.mean()), 4),
+        "host_threads_available": os.cpu_count(),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-plain", action="store_true", help="skip the non-compact comparator")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the load sweep")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (reference kernel for HBM byte counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path has no multi-GPU "
+              "sharding: every configuration is one GPU's share)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2406_09255_amd as cpht
+    import synth
+
+    dev = torch.device("cuda:0")
+    cpht.lib()  # the HIP library must be present: no fallback
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.int32, device=dev).fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": a.numel() * 4, "bytes_written": b.numel() * 4,
+                          "launches": 3}))
+        return
+
+    n_ins = int(LOAD * (1 << LOG2_SLOTS))
+    n_max = int(0.95 * (1 << LOG2_SLOTS))
+    keys64 = synth.distinct_keys(W_KEY, KEY_SEED, 0, n_max, device=dev)
+    queries64 = synth.find_queries(W_KEY, KEY_SEED, n_ins, N_FIND, 0.5, Q_SEED, device=dev)
+    keys = keys64.contiguous()
+    queries = queries64.contiguous()
+    torch.cuda.synchronize()
+
+    compact = cpht.Table(scheme=cpht.CUCKOO, key_bits=W_KEY, log2_slots0=LOG2_SLOTS, bucket0=BUCKET,
+                         slot_bits0=32, n_hash=2, max_chain=256, compact=1, seed=1)
+    run = Runner(torch, cpht, compact, keys, queries, n_ins)
+
+    for i in range(args.warmup):
+        run.step(seed=1000 + i, record=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        run.step(seed=1 + i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ins_ms, fnd_ms = run.times_ms()
+    wall = t1 - t0
+
+    # correctness guard on the last timed step (full check lives in the tests)
+    outs = run.out[:n_ins]
+    n_put = int((outs == cpht.PUT).sum().item())
+    hit = float(run.found.float().mean().item())
+    occ, cap = compact.count()
+    check = "ok" if (n_put == n_ins and occ == n_ins and abs(hit - 0.5) < 0.01) else "FAILED"
+
+    ms_step = wall * 1000.0 / args.steps
+    ops = n_ins + N_FIND
+    value = ops / (ms_step / 1000.0) / 1e6
+    ins_avg, fnd_avg = sum(ins_ms) / len(ins_ms), sum(fnd_ms) / len(fnd_ms)
+    res = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "Mops/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"compact cuckoo H=2, 2^{LOG2_SLOTS} slots in 2^{LOG2_SLOTS - 5} buckets of 32 x 32-bit "
+                         f"slots, {W_KEY}-bit keys in u64 words; per step: clear with a new seed, bulk build to "
+                         f"load {LOAD} ({n_ins} keys), then 2^26 finds (50% hit / 50% miss)"),
+            "slots": 1 << LOG2_SLOTS, "bucket": BUCKET, "slot_bits": 32, "key_bits": W_KEY, "load": LOAD,
+            "inserts": n_ins, "finds": N_FIND, "subtile": compact.config.subtile,
+        },
+        "check": check,
+        "insert_mops": round(n_ins / (ins_avg / 1000.0) / 1e6, 1),
+        "find_mops": round(N_FIND / (fnd_avg / 1000.0) / 1e6, 1),
+        "latency_ms": {
+            "insert": {"p50": round(pct(ins_ms, 50), 3), "p99": round(pct(ins_ms, 99), 3)},
+            "find": {"p50": round(pct(fnd_ms, 50), 3), "p99": round(pct(fnd_ms, 99), 3)},
+        },
+        "fill_factor": round(occ / cap, 4),
+        "table_bytes": compact.level_bytes(0),
+    }
+
+    # roofline of the dominant kernel (algorithmic bytes / average launch time)
+    kern = {
+        "cuckoo_put": (ins_avg, n_ins * put_bytes(LOAD, 1)),
+        "cuckoo_find": (fnd_avg, N_FIND * find_bytes(LOAD, 1)),
+    }
+    dom = max(kern, key=lambda k: kern[k][0])
+    rl = {}
+    for name, (ms, nbytes) in kern.items():
+        gbs = nbytes / (ms / 1000.0) / 1e9
+        rl[name] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "avg_ms": round(ms, 4),
+                    "algorithmic_bytes": int(nbytes)}
+    res["roofline"] = dict(rl[dom], kernel=dom)
+    res["roofline_other"] = {k: v for k, v in rl.items() if k != dom}
+    del compact
+
+    if not args.no_plain:
+        plain = cpht.Table(scheme=cpht.CUCKOO, key_bits=W_KEY, log2_slots0=LOG2_SLOTS, bucket0=BUCKET,
+                           slot_bits0=64, n_hash=2, max_chain=256, compact=0, seed=1)
+        prun = Runner(torch, cpht, plain, keys, queries, n_ins)
+        prun.step(seed=999, record=False)
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        for i in range(args.steps):
+            prun.step(seed=1 + i)
+        torch.cuda.synchronize()
+        p1 = time.perf_counter()
+        pins, pfnd = prun.times_ms()
+        pms = (p1 - p0) * 1000.0 / args.steps
+        pi, pf = sum(pins) / len(pins), sum(pfnd) / len(pfnd)
+        res["plain"] = {
+            "value": round(ops / (pms / 1000.0) / 1e6, 2), "ms_per_step": round(pms, 3),
+            "insert_mops": round(n_ins / (pi / 1000.0) / 1e6, 1), "find_mops": round(N_FIND / (pf / 1000.0) / 1e6, 1),
+            "latency_ms": {"insert": {"p50": round(pct(pins, 50), 3), "p99": round(pct(pins, 99), 3)},
+                           "find": {"p50": round(pct(pfnd, 50), 3), "p99": round(pct(pfnd, 99), 3)}},
+            "slot_bits": 64, "table_bytes": plain.level_bytes(0),
+        }
+        res["compact_vs_plain"] = {
+            "step": round(res["value"] / res["plain"]["value"], 3),
+            "insert": round(res["insert_mops"] / res["plain"]["insert_mops"], 3),
+            "find": round(res["find_mops"] / res["plain"]["find_mops"], 3),
+            "memory": round(res["table_bytes"] / res["plain"]["table_bytes"], 3),
+        }
+        del plain, prun
+
+    if not args.no_sweep:
+        sweep = []
+        for slot_bits, cmp_ in ((32, 1), (64, 0)):
+            if cmp_ == 0 and args.no_plain:
+                continue
+            t = cpht.Table(scheme=cpht.CUCKOO, key_bits=W_KEY, log2_slots0=LOG2_SLOTS, bucket0=BUCKET,
+                           slot_bits0=slot_bits, n_hash=2, max_chain=256, compact=cmp_, seed=1)
+            r = Runner(torch, cpht, t, keys, queries, 0)
+            for load in (0.5, 0.7, 0.8, 0.9, 0.95):
+                n = int(load * (1 << LOG2_SLOTS))
+                nq_hit = synth.find_queries(W_KEY, KEY_SEED, n, N_FIND, 0.5, Q_SEED + 7, device=dev)
+                r.queries = nq_hit
+                r.found = torch.empty(N_FIND, dtype=torch.uint8, device=dev)
+                for rep in range(3):
+                    r.step(seed=77 + rep, n_ins=n, record=rep > 0)
+                ins, fnd = r.times_ms()
+                full = int((r.out[:n] == cpht.FULL).sum().item())
+                sweep.append({"slot_bits": slot_bits, "compact": bool(cmp_), "load": load,
+                              "insert_mops": round(n / (sum(ins) / len(ins) / 1000.0) / 1e6, 1),
+                              "find_mops": round(N_FIND / (sum(fnd) / len(fnd) / 1000.0) / 1e6, 1),
+                              "full": full})
+            del t, r
+        res["sweep"] = sweep
+
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()
