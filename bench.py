@@ -42,11 +42,30 @@ ROUNDS_PER_PUT = {0.5: 1.00002, 0.7: 1.00252, 0.8: 1.01291, 0.9: 1.05175, 0.95: 
 PROBES_PER_FIND = {0.5: 1.00014, 0.7: 1.01809, 0.8: 1.07518, 0.9: 1.22454, 0.95: 1.36303}
 KEY_BYTES = 8
 RESULT_BYTES = 1
+SECTOR = 64  # write-back unit of a modified slot (measured: 68.7 B written per put at 1.05 rounds)
+
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by the
+# copy-kernel calibration factors 2.0 / 1.0), profiles/cuckoo_c2_hbm_bytes.md.
+# Valid only for the kernel sources they were taken with (hash below).
+TRAFFIC = {"csrc_sha": "5ff1a2c144aea60e", "cuckoo_put": 25937430028, "cuckoo_find": 11034506323}
+
+
+def csrc_sha() -> str:
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2406_09255_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def put_bytes(load: float, bucket_lines: int) -> float:
-    """Algorithmic bytes of one put: each round reads a bucket and writes one line."""
-    return ROUNDS_PER_PUT[load] * (bucket_lines + 1) * LINE + KEY_BYTES + RESULT_BYTES
+    """Algorithmic bytes of one put: each round reads a bucket and writes back
+    the 64-byte sector holding the claimed or swapped slot."""
+    return ROUNDS_PER_PUT[load] * (bucket_lines * LINE + SECTOR) + KEY_BYTES + RESULT_BYTES
 
 
 def find_bytes(load: float, bucket_lines: int) -> float:
@@ -129,6 +148,41 @@ def cpu_baseline(log2_slots: int = 25):
     }
 
 
+def ceilings(torch, cpht, dev, res):
+    """Measured random-access rates: 128-byte line reads, 32-bit CAS, and a
+    line read followed by a CAS into it, on a buffer the size of the compact
+    table (partly served by the 256 MB Infinity Cache) and on a 4 GiB buffer."""
+    out = {}
+    sink = torch.zeros(1, dtype=torch.int32, device=dev)
+    for label, nbytes in (("table_size", res["table_bytes"]), ("4GiB", 1 << 32)):
+        buf = torch.zeros(nbytes // 4, dtype=torch.int32, device=dev)
+        row = {}
+        for kind, name in ((cpht.PROBE_LINES, "line_reads"), (cpht.PROBE_CAS, "cas"),
+                           (cpht.PROBE_LINE_CAS, "line_read_then_cas")):
+            ops = 1 << 27
+            cpht.probe(kind, buf, ops, 1, sink)  # warm-up (and first touch)
+            times = []
+            for rep in range(3):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                done = cpht.probe(kind, buf, ops, 2 + rep, sink)
+                b.record()
+                b.synchronize()
+                times.append(a.elapsed_time(b))
+            ms = sorted(times)[1]
+            row[name] = {"G_per_s": round(done / (ms / 1000.0) / 1e9, 2), "ms": round(ms, 3)}
+        row["line_reads"]["GB_per_s"] = round(row["line_reads"]["G_per_s"] * 128, 1)
+        out[label] = row
+        del buf
+    # the benchmark's kernels against these ceilings (lines per op from the oracle model)
+    lines_put = ROUNDS_PER_PUT[LOAD]
+    lines_find = PROBES_PER_FIND[LOAD]
+    r = out["table_size"]
+    out["put_vs_line_read_then_cas"] = round(res["insert_mops"] * lines_put / (r["line_read_then_cas"]["G_per_s"] * 1e3), 3)
+    out["find_vs_line_reads"] = round(res["find_mops"] * lines_find / (r["line_reads"]["G_per_s"] * 1e3), 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +191,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the non-compact comparator")
     ap.add_argument("--no-sweep", action="store_true", help="skip the load sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-ceilings", action="store_true", help="skip the random-access ceiling probes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -235,12 +290,13 @@ def main():
         "cuckoo_find": (fnd_avg, N_FIND * find_bytes(LOAD, 1)),
     }
     dom = max(kern, key=lambda k: kern[k][0])
+    fresh = TRAFFIC["csrc_sha"] == csrc_sha()
     rl = {}
     for name, (ms, nbytes) in kern.items():
         gbs = nbytes / (ms / 1000.0) / 1e9
         rl[name] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "avg_ms": round(ms, 4),
-                    "algorithmic_bytes": int(nbytes)}
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": TRAFFIC[name] if fresh else None,
+                    "avg_ms": round(ms, 4), "algorithmic_bytes": int(nbytes)}
     res["roofline"] = dict(rl[dom], kernel=dom)
     res["roofline_other"] = {k: v for k, v in rl.items() if k != dom}
     del compact
@@ -297,6 +353,9 @@ def main():
                               "full": full})
             del t, r
         res["sweep"] = sweep
+
+    if not args.no_ceilings:
+        res["ceilings"] = ceilings(torch, cpht, dev, res)
 
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline()

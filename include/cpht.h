@@ -160,6 +160,17 @@ cpht_status_t cpht_split(cpht_table_t t, uint32_t perm_index, const void* d_keys
  * number of variants; fills *info (6 values) when info != NULL and i is valid. */
 int cpht_variant_info(uint32_t scheme, int i, uint32_t* info);
 
+/* Measurement kernels for the random-access roofline (not table operations).
+ * d_buf: device buffer of `bytes` bytes (a power of two, >= 4096), which the
+ * CAS kinds modify; d_sink: one device word the kernels may write.
+ *   kind 0: random 128-byte line reads, 8 lanes x 16 bytes per line;
+ *   kind 1: random 32-bit CAS (expected 0);
+ *   kind 2: a random line read followed by a CAS into that line.
+ * `ops` is rounded up to a multiple of 16384; *ops_done receives the count
+ * actually issued.  Asynchronous on `stream`. */
+cpht_status_t cpht_probe(uint32_t kind, void* d_buf, uint64_t bytes, uint64_t ops, uint64_t seed, uint32_t* d_sink,
+                         uint64_t* ops_done, void* stream);
+
 const char* cpht_status_str(cpht_status_t s);
 
 #ifdef __cplusplus

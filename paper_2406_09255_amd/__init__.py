@@ -75,6 +75,7 @@ _SIGNATURES = {
     "cpht_export": (_I32, [_VP, _U32, _VP, _U64]),
     "cpht_split": (_I32, [_VP, _U32, _VP, _U64, _VP, _VP, _VP]),
     "cpht_variant_info": (_I32, [_U32, _I32, ctypes.POINTER(_U32)]),
+    "cpht_probe": (_I32, [_U32, _VP, _U64, _U64, _U64, _VP, ctypes.POINTER(_U64), _VP]),
     "cpht_status_str": (ctypes.c_char_p, [_I32]),
 }
 
@@ -128,6 +129,17 @@ def variants(scheme: int) -> list[dict]:
         lib().cpht_variant_info(scheme, i, buf)
         out.append(dict(zip(("key64", "slot_bits0", "slot_bits1", "bucket0", "bucket1", "subtile"), list(buf))))
     return out
+
+
+PROBE_LINES, PROBE_CAS, PROBE_LINE_CAS = 0, 1, 2
+
+
+def probe(kind: int, buf: torch.Tensor, ops: int, seed: int, sink: torch.Tensor, stream=None) -> int:
+    """Launch a random-access roofline probe on `buf`; returns operations issued."""
+    done = _U64(0)
+    _check(lib().cpht_probe(kind, _dev_ptr(buf, "buf"), buf.numel() * buf.element_size(), ops, seed,
+                            _dev_ptr(sink, "sink"), ctypes.byref(done), _stream(stream)), "cpht_probe")
+    return done.value
 
 
 class Table:

@@ -10,6 +10,7 @@
 #include "cpht.h"
 #include "cpht_device.hpp"
 #include "cpht_registry.hpp"
+#include "cpht_roofline.hpp"
 #include "cpht_util.hpp"
 
 using namespace cpht;
@@ -397,6 +398,18 @@ int cpht_variant_info(uint32_t scheme, int i, uint32_t* info) {
     return 0;
   }
   return n32 + n64;
+}
+
+cpht_status_t cpht_probe(uint32_t kind, void* d_buf, uint64_t bytes, uint64_t ops, uint64_t seed, uint32_t* d_sink,
+                         uint64_t* ops_done, void* stream) {
+  if (kind > 2 || !d_buf || !d_sink || bytes < 4096 || !pow2(bytes) || ops == 0) return CPHT_E_ARG;
+  // whole 256-thread blocks: 16384 operations per block for every kind
+  const uint64_t unit = 16384;
+  const uint64_t n = (ops + unit - 1) / unit * unit;
+  hipError_t e = launch_probe((int)kind, d_buf, bytes, n, seed, d_sink, as_stream(stream));
+  if (e != hipSuccess) return device_status(e);
+  if (ops_done) *ops_done = n;
+  return CPHT_OK;
 }
 
 const char* cpht_status_str(cpht_status_t s) {

@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace cpht {
 
 // ---------------------------------------------------------------------------
@@ -163,12 +165,13 @@ __device__ __forceinline__ int lane_first_empty(const uint32_t (&w)[W], uint32_t
   return f;
 }
 
+// Word idx (a run-time value) of the lane's registers, selected with masks so
+// the register array is never indexed dynamically (which would spill it).
 template <int W>
 __device__ __forceinline__ uint32_t get_word(const uint32_t (&w)[W], int idx) {
-  uint32_t v = w[0];
+  uint32_t v = 0;
 #pragma unroll
-  for (int i = 1; i < W; ++i)
-    if (i == idx) v = w[i];
+  for (int i = 0; i < W; ++i) v |= w[i] & (0u - (uint32_t)(i == idx));
   return v;
 }
 
@@ -263,6 +266,55 @@ __device__ __forceinline__ int claim_slot(uint32_t* lane_ptr, const uint32_t (&w
   return got == e ? CLAIM_SAME : CLAIM_LOST;
 }
 
+// Claim slot q of the bucket starting at `bucket` for value e, by a single
+// lane on behalf of its own key (the pipelined paths let every key's owner
+// lane claim at once).  `word` is the snapshot of the 32-bit word holding the
+// slot (used by 16-bit slots only).  Same results as claim_slot.
+template <int S>
+__device__ __forceinline__ int claim_at(uint32_t* bucket, uint32_t q, uint32_t word, uint64_t e) {
+  uint64_t got;
+  if constexpr (S == 32) {
+    got = cas32(bucket + q, 0u, (uint32_t)e);
+  } else if constexpr (S == 64) {
+    got = cas64(reinterpret_cast<uint64_t*>(bucket + 2 * q), 0ull, e);
+  } else {
+    const uint32_t wi = q >> 1;
+    const int sh = (int)(q & 1u) * 16;
+    const uint32_t mine = (uint32_t)e << sh;
+    uint32_t cur = word & ~(0xFFFFu << sh);
+    for (;;) {
+      const uint32_t old = cas32(bucket + wi, cur, cur | mine);
+      if (old == cur) { got = 0; break; }
+      got = (old >> sh) & 0xFFFFu;
+      if (got) break;
+      cur = old;
+    }
+  }
+  if (got == 0) return CLAIM_WON;
+  return got == e ? CLAIM_SAME : CLAIM_LOST;
+}
+
+// Swap bucket slot q with value e (cuckoo eviction); returns the old value.
+template <int S>
+__device__ __forceinline__ uint64_t swap_at(uint32_t* bucket, uint32_t q, uint64_t e) {
+  static_assert(S == 32 || S == 64, "swap needs a native atomic exchange");
+  if constexpr (S == 32) return xchg32(bucket + q, (uint32_t)e);
+  else return xchg64(reinterpret_cast<uint64_t*>(bucket + 2 * q), e);
+}
+
+// Known-occupied mask of a bucket (one bit per slot), as broadcast within a
+// sub-tile: 32 bits for buckets of up to 32 slots, 64 bits otherwise.
+template <int B>
+using KnownMask = typename std::conditional<(B <= 32), uint32_t, uint64_t>::type;
+
+// The bits of a bucket mask that belong to the lane holding slots
+// [first, first + PER).
+template <int PER, class M>
+__device__ __forceinline__ uint32_t lane_bits(M mask, int first) {
+  const uint64_t m = (uint64_t)mask >> first;
+  return PER >= 32 ? (uint32_t)m : (uint32_t)(m & ((1ull << PER) - 1ull));
+}
+
 // ---------------------------------------------------------------------------
 // Sub-tile collectives over a 64-lane wavefront.  Every lane of a sub-tile
 // executes them together (control flow is uniform per sub-tile).
@@ -296,6 +348,16 @@ struct SubTile {
   }
   __device__ __forceinline__ bool bcast_bool(bool v, int src_rank) const {
     return bcast((uint32_t)v, src_rank) != 0u;
+  }
+  template <class M>
+  __device__ __forceinline__ M bcast_mask(M v, int src_rank) const {
+    if constexpr (sizeof(M) == 8) return (M)bcast64((uint64_t)v, src_rank);
+    else return (M)bcast((uint32_t)v, src_rank);
+  }
+  template <int S>
+  __device__ __forceinline__ uint64_t bcast_slot(uint64_t v, int src_rank) const {
+    if constexpr (S == 64) return bcast64(v, src_rank);
+    else return bcast((uint32_t)v, src_rank);
   }
 };
 

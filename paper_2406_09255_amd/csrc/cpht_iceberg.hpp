@@ -1,12 +1,22 @@
-// Compact two-level iceberg table: cooperative find-or-put (Sec. 3 Alg. 1 in
-// its cooperative form, Sec. 4.2 Alg. 2), lookup (Sec. 2.3), and the batch
-// work sharing of Sec. 4.2 Alg. 3 generalised to any batch size.
+// Compact two-level iceberg table: lockless find-or-put (Sec. 3 Alg. 1; its
+// cooperative form Sec. 4.2 Alg. 2), lookup (Sec. 2.3), and the batch work
+// sharing of Sec. 4.2 Alg. 3 for batches of any size.
 //
 // Sub-tile layout: G lanes read the primary bucket T0[a_0(k)] (W0 words per
 // lane, so B0 = G*W0*32/S0).  On the second level the sub-tile splits into two
 // contiguous halves; half h reads secondary bucket T1[a_{1+h}(k)] (W1 words
 // per lane, B1 = (G/2)*W1*32/S1).  The paper splits by even/odd rank; which
 // lanes serve which bucket does not change what is computed.
+//
+// Execution is organised in supersteps.  Each superstep has a level-1 part
+// and a level-2 part; in each part a sub-tile first issues the bucket loads of
+// all its keys that are at that level, then decides every key with sub-tile
+// ballots, and finally each key that needs a claim has its own lane CAS the
+// chosen slot, all owner lanes at once.  A lost claim marks that slot
+// known-occupied for the key and the key stays pending, so every superstep
+// either decides a key or learns one more occupied slot of its buckets; that
+// bounds a key to B0 + 2*B1 lost claims (the termination argument of the
+// proof in Appendix A), also when a re-read returns stale data.
 #pragma once
 #include "cpht_device.hpp"
 
@@ -26,111 +36,185 @@ struct IceShape {
   static_assert(PER0 * G == B0 && PER1 * HG == B1, "slots per lane");
 };
 
-// Second-level part of find-or-put (the level-2 loop of Alg. 1 / Alg. 2).
-// Both secondary buckets are snapshotted, one per half sub-tile.  FOUND if
-// either holds k's tagged remainder; otherwise the target is the first empty
-// slot of bucket 1 if that bucket is strictly less full than bucket 2, else
-// of bucket 2 (the least empty slot under the order of Appendix A, Def. 1);
-// FULL if the target bucket has no empty slot.  A lost claim merges the value
-// that won into the snapshot and the loop repeats.
-template <class U, int S0, int S1, int B0, int B1, int G>
-__device__ __forceinline__ uint8_t ice_level2(const TableK& T, const SubTile<G>& st, U k, bool insert) {
-  using Sh = IceShape<S0, S1, B0, B1, G>;
-  constexpr int HG = Sh::HG, W1 = Sh::W1, PER1 = Sh::PER1;
-  const int half = st.rk >= HG ? 1 : 0;
-  const int hr = st.rk & (HG - 1);
-  const LevelK& L = T.lv[1];
-  Split<U, S1> s = split_key<U, S1>(T, L, 1 + half, k, (uint32_t)half);
-  uint32_t* p = L.base + s.a * L.bucket_words + (uint32_t)(hr * W1);
-  uint32_t v[W1];
-  uint32_t known = 0;
-  load_words<W1>(v, p);
-  const uint32_t hmask = HG == 32 ? 0xFFFFFFFFu : ((1u << HG) - 1u);
-  for (;;) {
-    if (st.ballot(lane_has<S1, W1>(v, s.e))) return R_FOUND;
-    if (!insert) return 0;  // lookup: k is in neither secondary bucket
-    const int le = lane_first_empty<S1, W1>(v, known);
-    const uint32_t em = st.ballot(le < PER1);
-    const uint32_t em1 = em & hmask, em2 = em >> HG;
-    uint32_t l1 = B1, l2 = B1;
-    int f1 = 0, f2 = HG;
-    if (em1) { f1 = ctz32(em1); l1 = (uint32_t)(f1 * PER1) + st.bcast((uint32_t)le, f1); }
-    if (em2) { f2 = HG + ctz32(em2); l2 = (uint32_t)((f2 - HG) * PER1) + st.bcast((uint32_t)le, f2); }
-    const bool pick1 = l1 < l2;
-    if ((pick1 ? l1 : l2) == (uint32_t)B1) return R_FULL;
-    const int f = pick1 ? f1 : f2;
-    int claim = CLAIM_LOST;
-    if (st.rk == f) claim = claim_slot<S1, W1>(p, v, known, le, s.e);
-    claim = (int)st.bcast((uint32_t)claim, f);
-    if (claim == CLAIM_WON) return R_PUT;
-    if (claim == CLAIM_SAME) return R_FOUND;
-    uint32_t fr[W1];
-    load_words<W1>(fr, p);
-    merge_words<W1>(v, fr);
-  }
-}
+// Keys whose buckets one sub-tile loads together (buffers within 32
+// registers per lane).
+template <int G, int W>
+struct IceDepth {
+  static constexpr int D = G * W <= 32 ? G : (32 / W > 0 ? 32 / W : 1);
+  static_assert(G % D == 0, "prefetch depth must divide the sub-tile");
+};
 
-// Find-or-put (insert = true) or lookup (insert = false) of key k by the whole
-// sub-tile.  a0/e0 are k's primary bucket and stored form r_0(k).  The key
-// itself is only needed (for pi_1, pi_2) once the primary bucket is full.
-template <class U, int S0, int S1, int B0, int B1, int G>
-__device__ __forceinline__ uint8_t ice_op(const TableK& T, const SubTile<G>& st, U k_own, int t,
-                                          uint32_t a0, uint64_t e0, bool insert) {
-  using Sh = IceShape<S0, S1, B0, B1, G>;
-  constexpr int W0 = Sh::W0, PER0 = Sh::PER0;
-  const LevelK& L = T.lv[0];
-  uint32_t* p = L.base + (uint64_t)a0 * L.bucket_words + (uint32_t)(st.rk * W0);
-  uint32_t w[W0];
-  uint32_t known = 0;
-  load_words<W0>(w, p);
-  for (;;) {
-    if (st.ballot(lane_has<S0, W0>(w, e0))) return insert ? R_FOUND : 1;
-    const int le = lane_first_empty<S0, W0>(w, known);
-    const uint32_t em = st.ballot(le < PER0);
-    if (!em) break;           // primary full: go to level 2
-    if (!insert) return 0;    // lookup: a non-full primary bucket without k decides
-    const int f = ctz32(em);  // the lane holding the first empty slot
-    int claim = CLAIM_LOST;
-    if (st.rk == f) claim = claim_slot<S0, W0>(p, w, known, le, e0);
-    claim = (int)st.bcast((uint32_t)claim, f);
-    if (claim == CLAIM_WON) return R_PUT;
-    if (claim == CLAIM_SAME) return R_FOUND;
-    uint32_t fr[W0];
-    load_words<W0>(fr, p);
-    merge_words<W0>(w, fr);
-  }
-  U k;
-  if constexpr (sizeof(U) == 8) k = (U)st.bcast64((uint64_t)k_own, t);
-  else k = (U)st.bcast((uint32_t)k_own, t);
-  const uint8_t r = ice_level2<U, S0, S1, B0, B1, G>(T, st, k, insert);
-  return insert ? r : (r == R_FOUND ? 1 : 0);
-}
-
-// Batch kernel (Alg. 3): lane i owns key i (coalesced load) and its result
-// byte; each sub-tile serves the keys of its G lanes one after another.
+// Batch kernel.  Lane i owns key i (coalesced load) and its result byte.
+//   Level 1 (Alg. 1, first loop): k's remainder in the primary snapshot ->
+//     FOUND (lookup: 1); an empty slot -> lookup answers 0, find-or-put claims
+//     the first empty slot; primary full -> level 2.
+//   Level 2 (Alg. 1, second loop): k's tagged remainder in either secondary
+//     snapshot -> FOUND (lookup: 1; lookup otherwise 0); else the target is
+//     the first empty slot of bucket 1 if bucket 1 is strictly less full than
+//     bucket 2, else of bucket 2 (the least empty slot under the order of
+//     Appendix A, Def. 1); FULL if the target bucket has no empty slot.
+//   A claim that finds k's own stored form in the slot answers FOUND.
 // MODE_MIXED reads a per-key opcode (0 = find, 1 = find-or-put).
 template <class KeyT, int S0, int S1, int B0, int B1, int G, int MODE>
 __global__ __launch_bounds__(256) void iceberg_kernel(TableK T, BatchK Bt) {
   using U = KeyT;
+  using Sh = IceShape<S0, S1, B0, B1, G>;
+  using KM0 = KnownMask<B0>;
+  using KM1 = KnownMask<B1>;
+  constexpr int W0 = Sh::W0, W1 = Sh::W1, PER0 = Sh::PER0, PER1 = Sh::PER1, HG = Sh::HG;
+  constexpr int D0 = IceDepth<G, W0>::D, D1 = IceDepth<G, W1>::D;
   const SubTile<G> st;
+  const LevelK& L0 = T.lv[0];
+  const LevelK& L1 = T.lv[1];
   const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool act = idx < Bt.n;
   const U k = act ? static_cast<const U*>(Bt.keys)[idx] : (U)0;
-  uint32_t op = (uint32_t)MODE;
-  if constexpr (MODE == MODE_MIXED) op = act ? (uint32_t)Bt.ops[idx] : 0u;
-  const Split<U, S0> s0 = split_key<U, S0>(T, T.lv[0], 0, k, 0u);
+  bool ins = MODE == MODE_INSERT;
+  if constexpr (MODE == MODE_MIXED) ins = act && Bt.ops[idx] != 0;
+  const Split<U, S0> s0 = split_key<U, S0>(T, L0, 0, k, 0u);
+  Split<U, S1> s1{0, 0}, s2{0, 0};
+  bool have12 = false;
   uint8_t result = 0;
+  uint32_t stage = act ? 1u : 0u;  // 0 decided, 1 at level 1, 2 at level 2
+  KM0 known0 = 0;                  // primary slots known to be occupied
+  KM1 known1 = 0, known2 = 0;      // same for the two secondary buckets
+  const int half = st.rk >= HG ? 1 : 0;
+  const int hr = st.rk & (HG - 1);
+  const uint32_t hmask = HG == 32 ? 0xFFFFFFFFu : ((1u << HG) - 1u);
+
 #pragma unroll 1
-  for (int t = 0; t < G; ++t) {
-    if (!st.bcast_bool(act, t)) break;  // inactive lanes form the tail of the batch
-    const uint32_t a0 = st.bcast((uint32_t)s0.a, t);
-    uint64_t e0;
-    if constexpr (S0 == 64) e0 = st.bcast64(s0.e, t);
-    else e0 = st.bcast((uint32_t)s0.e, t);
-    bool ins = MODE == MODE_INSERT;
-    if constexpr (MODE == MODE_MIXED) ins = st.bcast(op, t) != 0u;
-    const uint8_t r = ice_op<U, S0, S1, B0, B1, G>(T, st, k, t, a0, e0, ins);
-    if (st.rk == t) result = r;
+  while (__ballot(stage != 0u) != 0ull) {
+    // ------------------------------------------------------------ level 1
+    if (__ballot(stage == 1u) != 0ull) {
+      bool claim = false;
+      uint32_t q = 0, word = 0;
+#pragma unroll 1
+      for (int t0 = 0; t0 < G; t0 += D0) {
+        uint32_t buf[D0][W0];
+        uint64_t ev[D0];
+        KM0 kn[D0];
+        bool live[D0];
+#pragma unroll
+        for (int d = 0; d < D0; ++d) {
+          live[d] = st.bcast(stage, t0 + d) == 1u;
+          const uint32_t a = st.bcast((uint32_t)s0.a, t0 + d);
+          ev[d] = st.template bcast_slot<S0>(s0.e, t0 + d);
+          if constexpr (MODE != MODE_FIND) kn[d] = st.bcast_mask(known0, t0 + d);
+          if (live[d]) load_words<W0>(buf[d], L0.base + (uint64_t)a * L0.bucket_words + (uint32_t)(st.rk * W0));
+        }
+#pragma unroll
+        for (int d = 0; d < D0; ++d) {
+          if (!live[d]) continue;
+          const bool mine = st.rk == t0 + d;
+          const bool ins_t = MODE == MODE_MIXED ? st.bcast_bool(ins, t0 + d) : MODE == MODE_INSERT;
+          if (st.ballot(lane_has<S0, W0>(buf[d], ev[d]))) {
+            if (mine) { result = ins_t ? R_FOUND : 1; stage = 0; }
+            continue;
+          }
+          KM0 knd = 0;
+          if constexpr (MODE != MODE_FIND) knd = kn[d];
+          const int le = lane_first_empty<S0, W0>(buf[d], ins_t ? lane_bits<PER0>(knd, st.rk * PER0) : 0u);
+          const uint32_t em = st.ballot(le < PER0);
+          if (!em) {
+            if (mine) stage = 2;  // primary full
+            continue;
+          }
+          if (!ins_t) {
+            if (mine) { result = 0; stage = 0; }
+            continue;
+          }
+          const int f = ctz32(em);
+          const uint32_t lef = st.bcast((uint32_t)le, f);
+          uint32_t wf = 0;
+          if constexpr (S0 == 16) wf = st.bcast(get_word<W0>(buf[d], (int)(lef >> 1)), f);
+          if (mine) { claim = true; q = (uint32_t)(f * PER0) + lef; word = wf; }
+        }
+      }
+      if constexpr (MODE != MODE_FIND) {
+        if (claim) {
+          const int r = claim_at<S0>(L0.base + s0.a * L0.bucket_words, q, word, s0.e);
+          if (r == CLAIM_WON) { result = R_PUT; stage = 0; }
+          else if (r == CLAIM_SAME) { result = R_FOUND; stage = 0; }
+          else known0 |= (KM0)1 << q;
+        }
+      }
+    }
+    // ------------------------------------------------------------ level 2
+    if (__ballot(stage == 2u) != 0ull) {
+      if (stage == 2u && !have12) {
+        s1 = split_key<U, S1>(T, L1, 1, k, 0u);
+        s2 = split_key<U, S1>(T, L1, 2, k, 1u);
+        have12 = true;
+      }
+      bool claim = false;
+      uint32_t q = 0, word = 0, pick2 = 0;
+#pragma unroll 1
+      for (int t0 = 0; t0 < G; t0 += D1) {
+        uint32_t buf[D1][W1];
+        uint64_t ev[D1];
+        KM1 kn[D1];
+        bool live[D1];
+#pragma unroll
+        for (int d = 0; d < D1; ++d) {
+          live[d] = st.bcast(stage, t0 + d) == 2u;
+          const uint32_t a1 = st.bcast((uint32_t)s1.a, t0 + d);
+          const uint32_t a2 = st.bcast((uint32_t)s2.a, t0 + d);
+          const uint64_t e1 = st.template bcast_slot<S1>(s1.e, t0 + d);
+          const uint64_t e2 = st.template bcast_slot<S1>(s2.e, t0 + d);
+          if constexpr (MODE != MODE_FIND) {
+            const KM1 k1 = st.bcast_mask(known1, t0 + d);
+            const KM1 k2 = st.bcast_mask(known2, t0 + d);
+            kn[d] = half ? k2 : k1;
+          }
+          ev[d] = half ? e2 : e1;
+          const uint32_t a = half ? a2 : a1;
+          if (live[d]) load_words<W1>(buf[d], L1.base + (uint64_t)a * L1.bucket_words + (uint32_t)(hr * W1));
+        }
+#pragma unroll
+        for (int d = 0; d < D1; ++d) {
+          if (!live[d]) continue;
+          const bool mine = st.rk == t0 + d;
+          const bool ins_t = MODE == MODE_MIXED ? st.bcast_bool(ins, t0 + d) : MODE == MODE_INSERT;
+          if (st.ballot(lane_has<S1, W1>(buf[d], ev[d]))) {
+            if (mine) { result = ins_t ? R_FOUND : 1; stage = 0; }
+            continue;
+          }
+          if (!ins_t) {
+            if (mine) { result = 0; stage = 0; }
+            continue;
+          }
+          KM1 knd = 0;
+          if constexpr (MODE != MODE_FIND) knd = kn[d];
+          const int le = lane_first_empty<S1, W1>(buf[d], lane_bits<PER1>(knd, hr * PER1));
+          const uint32_t em = st.ballot(le < PER1);
+          const uint32_t em1 = em & hmask, em2 = em >> HG;
+          uint32_t l1 = B1, l2 = B1;
+          int f1 = 0, f2 = HG;
+          if (em1) { f1 = ctz32(em1); l1 = (uint32_t)(f1 * PER1) + st.bcast((uint32_t)le, f1); }
+          if (em2) { f2 = HG + ctz32(em2); l2 = (uint32_t)((f2 - HG) * PER1) + st.bcast((uint32_t)le, f2); }
+          const bool p1 = l1 < l2;  // bucket 1 only if strictly less full (ties go to bucket 2)
+          const uint32_t lp = p1 ? l1 : l2;
+          if (lp == (uint32_t)B1) {
+            if (mine) { result = R_FULL; stage = 0; }
+            continue;
+          }
+          uint32_t wf = 0;
+          if constexpr (S1 == 16) wf = st.bcast(get_word<W1>(buf[d], (int)((lp % PER1) >> 1)), p1 ? f1 : f2);
+          if (mine) { claim = true; q = lp; word = wf; pick2 = p1 ? 0u : 1u; }
+        }
+      }
+      if constexpr (MODE != MODE_FIND) {
+        if (claim) {
+          const uint64_t ab = pick2 ? s2.a : s1.a;
+          const uint64_t e = pick2 ? s2.e : s1.e;
+          const int r = claim_at<S1>(L1.base + ab * L1.bucket_words, q, word, e);
+          if (r == CLAIM_WON) { result = R_PUT; stage = 0; }
+          else if (r == CLAIM_SAME) { result = R_FOUND; stage = 0; }
+          else if (pick2) known2 |= (KM1)1 << q;
+          else known1 |= (KM1)1 << q;
+        }
+      }
+    }
   }
   if (act) Bt.out[idx] = result;
 }

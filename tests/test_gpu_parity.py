@@ -375,3 +375,84 @@ def test_unsupported_configs_rejected(gpu):
     t = cuckoo(32, 12, 32, 32)
     with pytest.raises(cpht.CphtError):
         t.mixed(torch.zeros(4, dtype=torch.int32, device=gpu), torch.zeros(4, dtype=torch.uint8, device=gpu))
+
+
+# ---------------------------------------------------------------------------
+# contention: many keys of one batch aimed at the same few buckets
+# ---------------------------------------------------------------------------
+
+def _keys_in_buckets(t, level, perm_index, w, nbuckets, count, seed):
+    """Distinct keys whose bucket under perm_index is one of `nbuckets`
+    buckets (selected with the oracle's own split)."""
+    o = oracle_table(t)
+    cand = host_u64(synth.distinct_keys(w, seed, 0, 1 << 21))
+    a, _ = o.split(perm_index, cand)
+    chosen = np.unique(a)[:nbuckets]
+    pick = cand[np.isin(a, chosen)][:count]
+    assert pick.size == count
+    return torch.from_numpy(pick.astype(np.int64))
+
+
+@pytest.mark.parametrize("S0,S1", [(16, 32), (32, 32), (16, 16)])
+def test_iceberg_colliding_primary_buckets(gpu, S0, S1):
+    """Keys of a batch share 6 primary buckets, so claims collide, primaries
+    overflow into the secondary level and some keys come back FULL; keys are
+    also repeated.  Outcomes must still follow Theorem 1."""
+    w = 26 if S1 == 32 else 23
+    t = iceberg(w, 16, 32, S0, S1, seed=71)
+    base = _keys_in_buckets(t, 0, 0, w, 6, 600, 3)
+    keys = torch.cat([base, base[:200], base[::3]])[synth.permutation(5, 600 + 200 + 200)]
+    hk = host_u64(keys)
+    out = t.insert(to_dev(keys, w, gpu)).cpu().numpy()
+    dec = check_table(t)
+    uk, inv = np.unique(hk, return_inverse=True)
+    puts = np.bincount(inv, weights=(out == cpht.PUT), minlength=uk.size)
+    fulls = np.bincount(inv, weights=(out == cpht.FULL), minlength=uk.size)
+    cnt = np.bincount(inv, minlength=uk.size)
+    assert (puts <= 1).all() and ((puts == 1) | (fulls == cnt)).all()
+    assert np.array_equal(dec, np.sort(uk[puts == 1]))
+    img0, img1 = images(t)
+    ok, msg = oracle.check_full(oracle_cfg(t), img0, img1, uk[fulls > 0])
+    assert ok, msg
+    f = t.find(to_dev(keys, w, gpu)).cpu().numpy()
+    assert np.array_equal(f, np.isin(hk, dec).astype(np.uint8))
+
+
+def test_cuckoo_colliding_first_buckets(gpu):
+    """600 keys whose first bucket is one of 8 buckets: 256 fit there, the
+    rest are placed by evictions; no key may be lost."""
+    w = 30
+    t = cuckoo(w, 16, 32, 32, seed=72)
+    keys = _keys_in_buckets(t, 0, 0, w, 8, 600, 4)
+    out = t.bulk_build(to_dev(keys, w, gpu)).cpu().numpy()
+    dec = check_table(t)
+    nfull = int((out == cpht.FULL).sum())
+    assert dec.size == 600 - nfull and np.isin(dec, host_u64(keys)).all()
+    assert nfull == 0
+    f = t.find(to_dev(keys, w, gpu)).cpu().numpy()
+    assert (f == 1).all()
+
+
+def test_iceberg_high_load_parity(gpu):
+    """Fill a compact iceberg table (2^20 + 2^17 slots, B0 = 32) in 8 batches
+    of distinct keys to load 0.875; every batch must match the set semantics
+    unless FULL appears, and finds after each batch are bit-exact."""
+    w = 30
+    t = iceberg(w, 20, 32, 16, 32, seed=73)
+    cap = (1 << 20) + (1 << 17)
+    S_cur = np.zeros(0, np.uint64)
+    per = cap // 8
+    for b in range(7):
+        keys = synth.distinct_keys(w, KEY_SEED, b * per, per)
+        out = t.insert(to_dev(keys, w, gpu)).cpu().numpy()
+        hk = host_u64(keys)
+        if (out == cpht.FULL).any():
+            break
+        ok, msg = sets.check_insert_outcomes(S_cur, hk, out)
+        assert ok, msg
+        _, S_cur = sets.insert(S_cur, hk)
+        q = synth.find_queries(w, KEY_SEED, (b + 1) * per, 1 << 16, 0.5, b)
+        f = t.find(to_dev(q, w, gpu)).cpu().numpy()
+        assert np.array_equal(f, sets.find(S_cur, host_u64(q)))
+    assert np.array_equal(check_table(t), S_cur)
+    assert S_cur.size >= 6 * per
