@@ -148,6 +148,117 @@ def cpu_baseline(log2_slots: int = 25):
     }
 
 
+def iceberg_static(torch, cpht, synth, dev, reps=3):
+    """Iceberg Put / Find at the paper's Sec. 5.1 shape: 2^27 primary + 2^24
+    secondary slots, B0 = 32, B1 = 16, 37-bit keys; fill from empty to load
+    0.9 with distinct keys in one batch, then 2^26 finds at 50 % hit.
+    Compact 16/32-bit slots against plain 64/64-bit slots."""
+    w, L0, L1 = 37, 27, 24
+    cap = (1 << L0) + (1 << L1)
+    n = int(LOAD * cap)
+    keys = synth.distinct_keys(w, KEY_SEED + 1, 0, n, device=dev)
+    q = synth.find_queries(w, KEY_SEED + 1, n, N_FIND, 0.5, Q_SEED + 1, device=dev)
+    out = torch.empty(n, dtype=torch.uint8, device=dev)
+    found = torch.empty(N_FIND, dtype=torch.uint8, device=dev)
+    rows = {}
+    for label, s0, s1, cmp_ in (("compact_16_32", 16, 32, 1), ("plain_64_64", 64, 64, 0)):
+        t = cpht.Table(scheme=cpht.ICEBERG, key_bits=w, log2_slots0=L0, log2_slots1=L1, bucket0=32, bucket1=16,
+                       slot_bits0=s0, slot_bits1=s1, compact=cmp_, seed=5)
+        ins, fnd = [], []
+        for rep in range(reps + 1):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            t.clear(50 + rep)
+            e[0].record()
+            t.insert(keys, out)
+            e[1].record()
+            t.find(q, found)
+            e[2].record()
+            e[2].synchronize()
+            if rep:
+                ins.append(e[0].elapsed_time(e[1]))
+                fnd.append(e[1].elapsed_time(e[2]))
+        occ, cap_ = t.count()
+        nfull = int((out == cpht.FULL).sum().item())
+        ti, tf = sum(ins) / len(ins), sum(fnd) / len(fnd)
+        rows[label] = {"insert_mops": round(n / ti / 1e3, 1), "find_mops": round(N_FIND / tf / 1e3, 1),
+                       "insert_ms": round(ti, 3), "find_ms": round(tf, 3), "full": nfull,
+                       "fill_factor": round(occ / cap_, 4),
+                       "table_bytes": t.level_bytes(0) + t.level_bytes(1)}
+        del t
+    rows["compact_vs_plain"] = {
+        "insert": round(rows["compact_16_32"]["insert_mops"] / rows["plain_64_64"]["insert_mops"], 3),
+        "find": round(rows["compact_16_32"]["find_mops"] / rows["plain_64_64"]["find_mops"], 3),
+        "memory": round(rows["compact_16_32"]["table_bytes"] / rows["plain_64_64"]["table_bytes"], 4),
+    }
+    rows["config"] = (f"iceberg 2^{L0} + 2^{L1} slots, B0=32, B1=16, {w}-bit keys; insert {n} distinct keys "
+                      f"(load {LOAD}) in one batch, then 2^26 finds 50% hit")
+    return rows
+
+
+def iceberg_mixed(torch, cpht, synth, dev, log2_slots0=28, batch=1 << 20):
+    """Dynamic operation at 2^28 + 2^25 slots (B0 = 32, B1 = 16, 34-bit keys):
+    mixed batches of `batch` operations, half finds and half find-or-puts in
+    random order; 30 % of inserts repeat an earlier-issued key; finds hit keys
+    inserted by earlier batches half of the time.  Runs from load 0 to 0.9.
+    Reports ops/s over the whole run and the per-batch latency distribution."""
+    w = 34
+    L0, L1 = log2_slots0, log2_slots0 - 3
+    cap = (1 << L0) + (1 << L1)
+    half = batch // 2
+    fresh_per_batch = int(0.7 * half)
+    nb = int(LOAD * cap) // fresh_per_batch
+    n_ins = nb * half
+    ins, n_fresh = synth.insert_stream_with_duplicates(w, KEY_SEED + 3, 0, n_ins, 0.3, 11, device=dev)
+    rows = {}
+    # per batch: finds (half hits among keys issued by earlier batches, half misses)
+    g = synth.uniform_below(13, nb * half, 1 << 30, dev)
+    ins_b = ins.view(nb, half)
+    issued_before = torch.arange(nb, device=dev) * fresh_per_batch  # approximate count of fresh keys
+    hit_idx = (g.view(nb, half) * issued_before.clamp(min=1).view(nb, 1)) >> 30
+    hit_keys = synth.feistel(w, KEY_SEED + 3, hit_idx)
+    miss_keys = synth.distinct_keys(w, KEY_SEED + 3, 1 << 33, nb * half, device=dev).view(nb, half)
+    is_hit = (synth.uniform_below(17, nb * half, 2, dev).view(nb, half) == 1) & (issued_before.view(nb, 1) > 0)
+    finds = torch.where(is_hit, hit_keys, miss_keys)
+    keys = torch.cat([ins_b, finds], dim=1)
+    ops = torch.cat([torch.ones(nb, half, dtype=torch.uint8, device=dev),
+                     torch.zeros(nb, half, dtype=torch.uint8, device=dev)], dim=1)
+    perm = torch.stack([synth.permutation(100 + b, batch, dev) for b in range(min(nb, 8))])
+    idx = perm[torch.arange(nb, device=dev) % perm.shape[0]]
+    keys = torch.gather(keys, 1, idx).contiguous()
+    ops = torch.gather(ops, 1, idx).contiguous()
+    out = torch.empty(nb, batch, dtype=torch.uint8, device=dev)
+    del ins, hit_idx, hit_keys, miss_keys, finds, g
+    for label, s0, s1, cmp_ in (("compact_16_32", 16, 32, 1), ("plain_64_64", 64, 64, 0)):
+        t = cpht.Table(scheme=cpht.ICEBERG, key_bits=w, log2_slots0=L0, log2_slots1=L1, bucket0=32, bucket1=16,
+                       slot_bits0=s0, slot_bits1=s1, compact=cmp_, seed=9)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(nb + 1)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev[0].record()
+        for b in range(nb):
+            t.mixed(keys[b], ops[b], out[b])
+            ev[b + 1].record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lat = [ev[b].elapsed_time(ev[b + 1]) for b in range(nb)]
+        occ, cap_ = t.count()
+        nfull = int((out == cpht.FULL).sum().item())
+        first_full = None
+        if nfull:
+            first_full = int(torch.nonzero((out == cpht.FULL).any(dim=1))[0].item())
+        gpu_ms = ev[0].elapsed_time(ev[nb])
+        rows[label] = {"mops": round(nb * batch / gpu_ms / 1e3, 1), "wall_mops": round(nb * batch / wall / 1e6, 1),
+                       "batches": nb, "batch_ops": batch,
+                       "batch_latency_ms": {"p50": round(pct(lat, 50), 4), "p99": round(pct(lat, 99), 4)},
+                       "fill_factor": round(occ / cap_, 4), "full": nfull, "first_full_batch": first_full,
+                       "table_bytes": t.level_bytes(0) + t.level_bytes(1)}
+        del t
+    rows["compact_vs_plain"] = round(rows["compact_16_32"]["mops"] / rows["plain_64_64"]["mops"], 3)
+    rows["config"] = (f"iceberg 2^{L0} + 2^{L1} slots, B0=32, B1=16, {w}-bit keys; {nb} mixed batches of {batch} "
+                      f"ops (50% find / 50% find-or-put, 30% duplicate inserts, finds 50% hit), load 0 -> {LOAD}")
+    return rows
+
+
 def ceilings(torch, cpht, dev, res):
     """Measured random-access rates: 128-byte line reads, 32-bit CAS, and a
     line read followed by a CAS into it, on a buffer the size of the compact
@@ -192,6 +303,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the load sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ceilings", action="store_true", help="skip the random-access ceiling probes")
+    ap.add_argument("--no-iceberg", action="store_true", help="skip the iceberg sections")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -353,6 +465,10 @@ def main():
                               "full": full})
             del t, r
         res["sweep"] = sweep
+
+    if not args.no_iceberg:
+        res["iceberg_static"] = iceberg_static(torch, cpht, synth, dev)
+        res["iceberg_mixed"] = iceberg_mixed(torch, cpht, synth, dev)
 
     if not args.no_ceilings:
         res["ceilings"] = ceilings(torch, cpht, dev, res)
