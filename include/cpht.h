@@ -160,6 +160,52 @@ cpht_status_t cpht_split(cpht_table_t t, uint32_t perm_index, const void* d_keys
  * number of variants; fills *info (6 values) when info != NULL and i is valid. */
 int cpht_variant_info(uint32_t scheme, int i, uint32_t* info);
 
+/* ---- Table sets: many independent tables served by one launch -------------
+ * A table set owns one device arena holding every level of n tables whose
+ * configurations may differ (they must share the scheme and the key word size:
+ * all key_bits <= 32, or all > 32).  Tables are grouped by compiled kernel
+ * variant; a batch over the set is planned on the device (its keys cut into
+ * chunks of at most 256 keys of one table) and served by one persistent launch
+ * per variant group, so plan and launches contain no host step and can be
+ * captured in a single graph.  The set keeps device scratch for planning:
+ * batch calls on one set must be ordered on one stream (they are not safe to
+ * overlap).  Operations are those of cpht_insert / cpht_find, per table. */
+typedef struct cpht_multi* cpht_multi_t;
+
+/* Create a set of n_tables empty tables (synchronous).  max_keys bounds the
+ * keys of any single batch (it sizes the chunk list: max_keys/256 + n_tables
+ * chunks).  Each configuration is checked as by cpht_create. */
+cpht_status_t cpht_multi_create(uint32_t n_tables, const cpht_config_t* cfgs, uint64_t max_keys, cpht_multi_t* out);
+
+/* Free the set.  Pending work using it must have finished; views become invalid. */
+cpht_status_t cpht_multi_destroy(cpht_multi_t m);
+
+/* A non-owning handle to table i of the set, usable with every single-table
+ * call (insert, find, count, export, split, clear); cpht_destroy rejects it
+ * with CPHT_E_STATE. */
+cpht_status_t cpht_multi_table(cpht_multi_t m, uint32_t i, cpht_table_t* view);
+
+/* Empty every table (fill kernel on `stream`; permutation seeds unchanged). */
+cpht_status_t cpht_multi_clear(cpht_multi_t m, void* stream);
+
+/* Insert / find a batch over the set.  d_keys holds the keys of all tables
+ * concatenated; d_offsets (device, n_tables + 1 entries) gives table i the
+ * keys [d_offsets[i], d_offsets[i+1]); total_keys is the length of d_keys
+ * (keys at or past it are ignored; at most max_keys).  d_out has one byte per
+ * key at the same index, with the single-table meaning.  If the chunks of a
+ * batch exceed the capacity, the excess is skipped and bit 0 of the flags of
+ * cpht_multi_error is raised. */
+cpht_status_t cpht_multi_insert(cpht_multi_t m, const void* d_keys, const uint64_t* d_offsets, uint64_t total_keys,
+                                uint8_t* d_out, void* stream);
+cpht_status_t cpht_multi_find(cpht_multi_t m, const void* d_keys, const uint64_t* d_offsets, uint64_t total_keys,
+                              uint8_t* d_found, void* stream);
+
+/* Arena size, number of variant groups (= launches per batch), chunk capacity. */
+cpht_status_t cpht_multi_info(cpht_multi_t m, uint64_t* arena_bytes, uint32_t* n_groups, uint64_t* max_chunks);
+
+/* Synchronise the device, return and clear the set's error flags. */
+cpht_status_t cpht_multi_error(cpht_multi_t m, uint32_t* flags);
+
 /* Measurement kernels for the random-access roofline (not table operations).
  * d_buf: device buffer of `bytes` bytes (a power of two, >= 4096), which the
  * CAS kinds modify; d_sink: one device word the kernels may write.

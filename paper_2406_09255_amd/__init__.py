@@ -76,6 +76,14 @@ _SIGNATURES = {
     "cpht_split": (_I32, [_VP, _U32, _VP, _U64, _VP, _VP, _VP]),
     "cpht_variant_info": (_I32, [_U32, _I32, ctypes.POINTER(_U32)]),
     "cpht_probe": (_I32, [_U32, _VP, _U64, _U64, _U64, _VP, ctypes.POINTER(_U64), _VP]),
+    "cpht_multi_create": (_I32, [_U32, _VP, _U64, ctypes.POINTER(_VP)]),
+    "cpht_multi_destroy": (_I32, [_VP]),
+    "cpht_multi_table": (_I32, [_VP, _U32, ctypes.POINTER(_VP)]),
+    "cpht_multi_clear": (_I32, [_VP, _VP]),
+    "cpht_multi_insert": (_I32, [_VP, _VP, _VP, _U64, _VP, _VP]),
+    "cpht_multi_find": (_I32, [_VP, _VP, _VP, _U64, _VP, _VP]),
+    "cpht_multi_info": (_I32, [_VP, ctypes.POINTER(_U64), ctypes.POINTER(_U32), ctypes.POINTER(_U64)]),
+    "cpht_multi_error": (_I32, [_VP, ctypes.POINTER(_U32)]),
     "cpht_status_str": (ctypes.c_char_p, [_I32]),
 }
 
@@ -145,6 +153,15 @@ def probe(kind: int, buf: torch.Tensor, ops: int, seed: int, sink: torch.Tensor,
 class Table:
     """One compact hash table resident in device memory (cpht_table_t)."""
 
+    @classmethod
+    def _view(cls, handle, owner) -> "Table":
+        t = cls.__new__(cls)
+        t._h = handle
+        t._owner = owner  # keeps the table set alive; views are never destroyed
+        t.config = Config()
+        _check(lib().cpht_get_config(t._h, ctypes.byref(t.config)), "cpht_get_config")
+        return t
+
     def __init__(self, config: Config | None = None, **fields):
         scheme = fields.get("scheme", config.scheme if config is not None else CUCKOO)
         cfg = Config()
@@ -162,9 +179,9 @@ class Table:
 
     # -- lifetime -----------------------------------------------------------
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and getattr(self, "_owner", None) is None:
             lib().cpht_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         try:
@@ -267,3 +284,67 @@ class Table:
         buf = np.empty(nbytes, dtype=np.uint8)
         _check(lib().cpht_export(self._h, level, buf.ctypes.data_as(_VP), nbytes), "cpht_export")
         return buf
+
+
+class MultiTable:
+    """A set of independent tables served by one launch per kernel variant
+    (cpht_multi_t).  `configs` is a list of Config; batches are CSR: the keys
+    of all tables concatenated plus int64 device offsets (n + 1)."""
+
+    def __init__(self, configs, max_keys: int):
+        arr = (Config * len(configs))()
+        for i, c in enumerate(configs):
+            ctypes.memmove(ctypes.byref(arr[i]), ctypes.byref(c), ctypes.sizeof(Config))
+        h = _VP()
+        _check(lib().cpht_multi_create(len(configs), ctypes.cast(arr, _VP), max_keys, ctypes.byref(h)),
+               "cpht_multi_create")
+        self._h = h
+        self.n = len(configs)
+        self.key_dtype = torch.int32 if configs[0].key_bits <= 32 else torch.int64
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cpht_multi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def table(self, i: int) -> Table:
+        v = _VP()
+        _check(lib().cpht_multi_table(self._h, i, ctypes.byref(v)), "cpht_multi_table")
+        return Table._view(v, self)
+
+    def info(self) -> dict:
+        a, g, c = _U64(0), _U32(0), _U64(0)
+        _check(lib().cpht_multi_info(self._h, ctypes.byref(a), ctypes.byref(g), ctypes.byref(c)), "cpht_multi_info")
+        return {"arena_bytes": a.value, "groups": g.value, "max_chunks": c.value}
+
+    def clear(self, stream=None):
+        _check(lib().cpht_multi_clear(self._h, _stream(stream)), "cpht_multi_clear")
+
+    def _run(self, fn, name, keys, offsets, out, stream):
+        if keys.dtype != self.key_dtype:
+            raise ValueError(f"keys must be {self.key_dtype}")
+        if offsets.dtype != torch.int64 or offsets.numel() != self.n + 1:
+            raise ValueError("offsets must be int64 with n_tables + 1 entries")
+        n = keys.numel()
+        if out is None:
+            out = torch.empty(n, dtype=torch.uint8, device=keys.device)
+        _check(fn(self._h, _dev_ptr(keys, "keys"), _dev_ptr(offsets, "offsets"), n, _dev_ptr(out, "out"),
+                  _stream(stream)), name)
+        return out
+
+    def insert(self, keys, offsets, out=None, stream=None):
+        return self._run(lib().cpht_multi_insert, "cpht_multi_insert", keys, offsets, out, stream)
+
+    def find(self, keys, offsets, out=None, stream=None):
+        return self._run(lib().cpht_multi_find, "cpht_multi_find", keys, offsets, out, stream)
+
+    def error_flags(self) -> int:
+        f = _U32(0)
+        _check(lib().cpht_multi_error(self._h, ctypes.byref(f)), "cpht_multi_error")
+        return f.value

@@ -12,23 +12,11 @@
 #include "cpht_registry.hpp"
 #include "cpht_roofline.hpp"
 #include "cpht_util.hpp"
+#include "cpht_internal.hpp"
 
 using namespace cpht;
 
-struct cpht_table {
-  cpht_config_t cfg;
-  int device;
-  int nlevels;
-  uint32_t* level[2];
-  uint64_t level_words[2];
-  uint32_t slot_bits[2];
-  unsigned long long* d_counter;
-  TableK tk;
-  const IceVariant* ice;
-  const CkVariant* ck;
-};
-
-namespace {
+namespace cpht {
 
 // splitmix64 (Vigna): output number i+1 of the generator started at `seed`.
 uint64_t splitmix(uint64_t seed, uint64_t i) {
@@ -72,27 +60,22 @@ uint32_t log2_exact(uint64_t v) {
 }
 bool pow2(uint64_t v) { return v && !(v & (v - 1)); }
 
-hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
-
 cpht_status_t device_status(hipError_t e) {
   if (e == hipSuccess) return CPHT_OK;
   if (e == hipErrorOutOfMemory) return CPHT_E_NOMEM;
   return CPHT_E_DEVICE;
 }
 
-// Make the table's device current for the duration of a call.
-struct DeviceGuard {
-  int prev = -1;
-  bool ok = true;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
-    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
+DeviceGuard::DeviceGuard(int dev) {
+  if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+  if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+}
+DeviceGuard::~DeviceGuard() {
+  int cur = -1;
+  if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+}
+
+namespace {
 
 // Fill in one level of the kernel view; returns false if the stored form
 // (payload + tag + occupancy bit) does not fit the slot.
@@ -138,6 +121,56 @@ const CkVariant* find_ck(int key64, const cpht_config_t& c) {
   return nullptr;
 }
 
+}  // namespace
+
+cpht_status_t configure_table(cpht_table* t, const cpht_config_t& c) {
+  if (c.scheme != CPHT_CUCKOO && c.scheme != CPHT_ICEBERG) return CPHT_E_ARG;
+  if (c.key_bits < 1 || c.key_bits > 64) return CPHT_E_ARG;
+  if (c.compact > 1) return CPHT_E_ARG;
+  t->cfg = c;
+  const int key64 = c.key_bits > 32;
+  TableK& K = t->tk;
+  std::memset(&K, 0, sizeof(K));
+  K.w = c.key_bits;
+  K.h = (c.key_bits + 1) / 2;
+  K.kmask = mask_bits(c.key_bits);
+  K.compact = c.compact;
+  bool ok = true;
+  if (c.scheme == CPHT_CUCKOO) {
+    if (c.n_hash < 2 || c.n_hash > 3 || c.max_chain < 1) ok = false;
+    K.H = c.n_hash;
+    K.C = c.max_chain;
+    t->nlevels = 1;
+    ok = ok && level_view(t, 0, c.log2_slots0, c.bucket0, c.slot_bits0, log2_exact(c.n_hash));
+    if (ok) {
+      t->ck = find_ck(key64, c);
+      ok = t->ck != nullptr;
+      if (ok) t->cfg.subtile = (uint32_t)t->ck->G;
+    }
+    t->cfg.log2_slots1 = 0;
+    t->cfg.bucket1 = 0;
+  } else {
+    t->nlevels = 2;
+    ok = c.bucket1 * 2 == c.bucket0;
+    ok = ok && level_view(t, 0, c.log2_slots0, c.bucket0, c.slot_bits0, 0);
+    ok = ok && level_view(t, 1, c.log2_slots1, c.bucket1, c.slot_bits1, 1);
+    if (ok) {
+      t->ice = find_ice(key64, c);
+      ok = t->ice != nullptr;
+      if (ok) t->cfg.subtile = (uint32_t)t->ice->G;
+    }
+  }
+  if (!ok) return CPHT_E_UNSUPPORTED;
+  derive_perms(t, c.seed);
+  return CPHT_OK;
+}
+
+}  // namespace cpht
+
+namespace {
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
 BatchK batch(const void* keys, const uint8_t* ops, uint8_t* out, uint64_t n) {
   BatchK b;
   b.keys = keys;
@@ -179,52 +212,15 @@ void cpht_config_default(uint32_t scheme, cpht_config_t* c) {
 cpht_status_t cpht_create(const cpht_config_t* cfg, cpht_table_t* out) {
   if (!cfg || !out) return CPHT_E_ARG;
   *out = nullptr;
-  const cpht_config_t& c = *cfg;
-  if (c.scheme != CPHT_CUCKOO && c.scheme != CPHT_ICEBERG) return CPHT_E_ARG;
-  if (c.key_bits < 1 || c.key_bits > 64) return CPHT_E_ARG;
-  if (c.compact > 1) return CPHT_E_ARG;
-
   cpht_table* t = new (std::nothrow) cpht_table();
   if (!t) return CPHT_E_NOMEM;
-  t->cfg = c;
-  const int key64 = c.key_bits > 32;
-  TableK& K = t->tk;
-  std::memset(&K, 0, sizeof(K));
-  K.w = c.key_bits;
-  K.h = (c.key_bits + 1) / 2;
-  K.kmask = mask_bits(c.key_bits);
-  K.compact = c.compact;
-
-  bool ok = true;
-  if (c.scheme == CPHT_CUCKOO) {
-    if (c.n_hash < 2 || c.n_hash > 3 || c.max_chain < 1) ok = false;
-    K.H = c.n_hash;
-    K.C = c.max_chain;
-    t->nlevels = 1;
-    ok = ok && level_view(t, 0, c.log2_slots0, c.bucket0, c.slot_bits0, log2_exact(c.n_hash));
-    if (ok) {
-      t->ck = find_ck(key64, c);
-      ok = t->ck != nullptr;
-      if (ok) t->cfg.subtile = (uint32_t)t->ck->G;
-    }
-    t->cfg.log2_slots1 = 0;
-    t->cfg.bucket1 = 0;
-  } else {
-    t->nlevels = 2;
-    ok = c.bucket1 * 2 == c.bucket0;
-    ok = ok && level_view(t, 0, c.log2_slots0, c.bucket0, c.slot_bits0, 0);
-    ok = ok && level_view(t, 1, c.log2_slots1, c.bucket1, c.slot_bits1, 1);
-    if (ok) {
-      t->ice = find_ice(key64, c);
-      ok = t->ice != nullptr;
-      if (ok) t->cfg.subtile = (uint32_t)t->ice->G;
-    }
-  }
-  if (!ok) {
+  const cpht_status_t st = configure_table(t, *cfg);
+  if (st != CPHT_OK) {
     delete t;
-    return CPHT_E_UNSUPPORTED;
+    return st;
   }
-  derive_perms(t, c.seed);
+  TableK& K = t->tk;
+  t->owns_memory = true;
 
   if (hipGetDevice(&t->device) != hipSuccess) {
     delete t;
@@ -251,6 +247,7 @@ cpht_status_t cpht_create(const cpht_config_t* cfg, cpht_table_t* out) {
 
 cpht_status_t cpht_destroy(cpht_table_t t) {
   if (!t) return CPHT_E_ARG;
+  if (!t->owns_memory) return CPHT_E_STATE;  // a view into a table set
   DeviceGuard g(t->device);
   for (int x = 0; x < 2; ++x)
     if (t->level[x]) (void)hipFree(t->level[x]);

@@ -45,14 +45,13 @@ struct Depth {
 //     continues as key pi_{j'}^{-1}(a . r') with hash index j'+1 mod H.
 //     After C rounds the carried key is dropped and the result is FULL.
 template <class KeyT, int S, int B, int G, bool PUT>
-__global__ __launch_bounds__(256) void cuckoo_kernel(TableK T, BatchK Bt) {
+__device__ __forceinline__ void cuckoo_body(const TableK& T, const BatchK& Bt, uint64_t idx) {
   using U = KeyT;
   using Sh = CkShape<S, B, G>;
   using KM = KnownMask<B>;
   constexpr int W = Sh::W, PER = Sh::PER, D = Depth<G, W>::D;
   const SubTile<G> st;
   const LevelK& L = T.lv[0];
-  const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool act = idx < Bt.n;
   U k = act ? static_cast<const U*>(Bt.keys)[idx] : (U)0;
   Split<U, S> s = split_key<U, S>(T, L, 0, k, 0u);
@@ -134,6 +133,29 @@ __global__ __launch_bounds__(256) void cuckoo_kernel(TableK T, BatchK Bt) {
     }
   }
   if (act) Bt.out[idx] = result;
+}
+
+// One table: key i of the batch is handled by global thread i.
+template <class KeyT, int S, int B, int G, bool PUT>
+__global__ __launch_bounds__(256) void cuckoo_kernel(TableK T, BatchK Bt) {
+  cuckoo_body<KeyT, S, B, G, PUT>(T, Bt, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Many tables in one persistent launch (see iceberg_multi_kernel).
+template <class KeyT, int S, int B, int G, bool PUT>
+__global__ __launch_bounds__(256) void cuckoo_multi_kernel(MultiK M) {
+  const uint64_t first = M.group[0], count = M.group[1];
+#pragma unroll 1
+  for (uint64_t c = blockIdx.x; c < count; c += gridDim.x) {
+    const ChunkK ch = M.chunks[first + c];
+    const TableK& T = M.descs[ch.table];
+    BatchK Bt;
+    Bt.keys = static_cast<const KeyT*>(M.keys) + ch.start;
+    Bt.ops = nullptr;
+    Bt.out = M.out + ch.start;
+    Bt.n = ch.count;
+    cuckoo_body<KeyT, S, B, G, PUT>(T, Bt, threadIdx.x);
+  }
 }
 
 }  // namespace cpht

@@ -52,6 +52,22 @@ struct BatchK {
   uint64_t n;
 };
 
+// A launch over many tables: chunk b = keys [start, start + count) of the
+// concatenated key array, all of table `table` (count <= 256).
+struct ChunkK {
+  uint64_t start;
+  uint32_t table;
+  uint32_t count;
+};
+
+struct MultiK {
+  const TableK* descs;     // one description per table (device memory)
+  const ChunkK* chunks;    // all chunks, grouped by kernel variant
+  const uint64_t* group;   // device pair: first chunk and chunk count of this launch's group
+  const void* keys;        // concatenated keys of all tables
+  uint8_t* out;            // one result byte per key, same indexing
+};
+
 enum : uint8_t { R_NONE = 0, R_PUT = 1, R_FOUND = 2, R_FULL = 3 };
 
 // ---------------------------------------------------------------------------

@@ -56,7 +56,7 @@ struct IceDepth {
 //   A claim that finds k's own stored form in the slot answers FOUND.
 // MODE_MIXED reads a per-key opcode (0 = find, 1 = find-or-put).
 template <class KeyT, int S0, int S1, int B0, int B1, int G, int MODE>
-__global__ __launch_bounds__(256) void iceberg_kernel(TableK T, BatchK Bt) {
+__device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, uint64_t idx) {
   using U = KeyT;
   using Sh = IceShape<S0, S1, B0, B1, G>;
   using KM0 = KnownMask<B0>;
@@ -66,7 +66,6 @@ __global__ __launch_bounds__(256) void iceberg_kernel(TableK T, BatchK Bt) {
   const SubTile<G> st;
   const LevelK& L0 = T.lv[0];
   const LevelK& L1 = T.lv[1];
-  const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool act = idx < Bt.n;
   const U k = act ? static_cast<const U*>(Bt.keys)[idx] : (U)0;
   bool ins = MODE == MODE_INSERT;
@@ -217,6 +216,31 @@ __global__ __launch_bounds__(256) void iceberg_kernel(TableK T, BatchK Bt) {
     }
   }
   if (act) Bt.out[idx] = result;
+}
+
+// One table: key i of the batch is handled by global thread i.
+template <class KeyT, int S0, int S1, int B0, int B1, int G, int MODE>
+__global__ __launch_bounds__(256) void iceberg_kernel(TableK T, BatchK Bt) {
+  iceberg_body<KeyT, S0, S1, B0, B1, G, MODE>(T, Bt, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Many tables in one persistent launch: a fixed grid of blocks walks the
+// chunks of its variant group (each chunk = up to 256 consecutive keys of one
+// table), reading that table's description from device memory.
+template <class KeyT, int S0, int S1, int B0, int B1, int G, int MODE>
+__global__ __launch_bounds__(256) void iceberg_multi_kernel(MultiK M) {
+  const uint64_t first = M.group[0], count = M.group[1];
+#pragma unroll 1
+  for (uint64_t c = blockIdx.x; c < count; c += gridDim.x) {
+    const ChunkK ch = M.chunks[first + c];
+    const TableK& T = M.descs[ch.table];
+    BatchK Bt;
+    Bt.keys = static_cast<const KeyT*>(M.keys) + ch.start;
+    Bt.ops = nullptr;
+    Bt.out = M.out + ch.start;
+    Bt.n = ch.count;
+    iceberg_body<KeyT, S0, S1, B0, B1, G, MODE>(T, Bt, threadIdx.x);
+  }
 }
 
 }  // namespace cpht

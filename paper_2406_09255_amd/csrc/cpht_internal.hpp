@@ -1,0 +1,48 @@
+// Host-side internals shared by the C-ABI source files.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "cpht.h"
+#include "cpht_device.hpp"
+#include "cpht_registry.hpp"
+
+// One table: its resolved configuration, kernel view and device memory.
+struct cpht_table {
+  cpht_config_t cfg;
+  int device;
+  int nlevels;
+  bool owns_memory;
+  uint32_t* level[2];
+  uint64_t level_words[2];
+  uint32_t slot_bits[2];
+  unsigned long long* d_counter;
+  cpht::TableK tk;
+  const cpht::IceVariant* ice;
+  const cpht::CkVariant* ck;
+};
+
+namespace cpht {
+
+uint64_t splitmix(uint64_t seed, uint64_t i);
+uint64_t mask_bits(uint32_t w);
+uint64_t inverse_odd(uint64_t m);
+void derive_perms(cpht_table* t, uint64_t seed);
+uint32_t log2_exact(uint64_t v);
+bool pow2(uint64_t v);
+cpht_status_t device_status(hipError_t e);
+
+// Validate `c`, resolve the kernel variant and fill t's kernel view (level
+// sizes, payload widths, permutation constants).  Allocates nothing.
+cpht_status_t configure_table(cpht_table* t, const cpht_config_t& c);
+
+// Makes a device current for the lifetime of the guard.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev);
+  ~DeviceGuard();
+};
+
+}  // namespace cpht

@@ -7,18 +7,21 @@
 namespace cpht {
 
 typedef void (*launch_fn)(const TableK&, const BatchK&, hipStream_t);
+typedef void (*multi_fn)(const MultiK&, uint32_t blocks, hipStream_t);
 
 struct IceVariant {
   int key64;           // 1: 64-bit key words
   int S0, S1, B0, B1;  // slot bits and bucket slots per level
   int G;               // sub-tile lanes
   launch_fn find, insert, mixed;
+  multi_fn multi_find, multi_insert;
 };
 
 struct CkVariant {
   int key64;
   int S, B, G;
   launch_fn put, find;
+  multi_fn multi_put, multi_find;
 };
 
 // Iceberg variants: (S0, S1, B0, G) with B1 = B0 / 2.  The first entry for a
@@ -46,6 +49,12 @@ template <class Kern>
 inline void launch_grid(Kern k, const TableK& T, const BatchK& B, hipStream_t s) {
   const uint64_t blocks = (B.n + 255) / 256;
   hipLaunchKernelGGL(k, dim3((uint32_t)blocks), dim3(256), 0, s, T, B);
+}
+
+// `blocks` is the fixed (persistent) grid; the blocks walk the group's chunks.
+template <class Kern>
+inline void launch_chunks(Kern k, const MultiK& M, uint32_t blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, s, M);
 }
 
 }  // namespace cpht
