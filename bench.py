@@ -259,6 +259,114 @@ def iceberg_mixed(torch, cpht, synth, dev, log2_slots0=28, batch=1 << 20):
     return rows
 
 
+def many_tables(torch, cpht, synth, dev, n_tables=4096, lo=10, hi=20, load=0.85, reps=3):
+    """Many-table workload: n_tables independent compact iceberg tables with
+    2^e + 2^(e-3) slots, e uniform in lo..hi, 32-bit keys; each table is filled
+    to `load` with distinct keys and then queried with twice its capacity in
+    finds (50 % hit).  The autotuner picks each size class's kernel variant.
+    Timed three ways: table-set launches (plan + one persistent launch per
+    variant group), the same captured once in a graph and replayed, and one
+    single-table launch per table."""
+    from paper_2406_09255_amd import tune
+
+    w = 32
+    e_t = (synth.uniform_below(0xE5, n_tables, hi - lo + 1, dev) + lo).cpu().tolist()
+    t0 = time.perf_counter()
+    chosen, tried = tune.tune_set(cpht.ICEBERG, w, e_t, load, device=dev)
+    tune_s = time.perf_counter() - t0
+    cfgs = []
+    for i, e in enumerate(e_t):
+        c = cpht.default_config(cpht.ICEBERG)
+        c.key_bits = w
+        c.log2_slots0, c.log2_slots1 = e, e - 3
+        c.bucket0, c.slot_bits0, c.slot_bits1, c.subtile = (chosen["bucket0"], chosen["slot_bits0"],
+                                                           chosen["slot_bits1"], chosen["subtile"])
+        c.bucket1 = c.bucket0 // 2
+        c.seed = 7000 + i
+        cfgs.append(c)
+    cap = torch.tensor([(1 << e) + (1 << (e - 3)) for e in e_t], dtype=torch.int64, device=dev)
+    n_t = (cap.double() * load).long()
+    q_t = 2 * cap
+    ko = torch.zeros(n_tables + 1, dtype=torch.int64, device=dev)
+    ko[1:] = torch.cumsum(n_t, 0)
+    qo = torch.zeros(n_tables + 1, dtype=torch.int64, device=dev)
+    qo[1:] = torch.cumsum(q_t, 0)
+    total_k, total_q = int(ko[-1]), int(qo[-1])
+    keys64 = synth.distinct_keys(w, KEY_SEED + 9, 0, total_k, device=dev)
+    tid = torch.repeat_interleave(torch.arange(n_tables, device=dev), q_t)
+    pick = ko[tid] + ((synth.uniform_below(0xAB, total_q, 1 << 30, dev) * n_t[tid]) >> 30)
+    hit = synth.uniform_below(0xCD, total_q, 2, dev) == 1
+    miss = synth.distinct_keys(w, KEY_SEED + 9, total_k, total_q, device=dev)
+    queries = synth.to_words(torch.where(hit, keys64[pick], miss), w).contiguous()
+    keys = synth.to_words(keys64, w).contiguous()
+    del keys64, tid, pick, hit, miss
+    m = cpht.MultiTable(cfgs, max_keys=max(total_k, total_q))
+    info = m.info()
+    out = torch.empty(total_k, dtype=torch.uint8, device=dev)
+    found = torch.empty(total_q, dtype=torch.uint8, device=dev)
+    ops = total_k + total_q
+
+    def timed(fn, n):
+        ts = []
+        for _ in range(n):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            m.clear()
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        return sorted(ts)[len(ts) // 2]
+
+    def set_launch():
+        m.insert(keys, ko, out)
+        m.find(queries, qo, found)
+
+    set_launch()
+    set_ms = timed(set_launch, reps)
+    n_put = int((out == cpht.PUT).sum().item())
+    n_full = int((out == cpht.FULL).sum().item())
+    ok = n_put + n_full == total_k  # FULL is a valid answer of a two-level table near its limit
+    hit_frac = float(found.float().mean().item())
+
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            m.insert(keys, ko, out, stream=s)
+            m.find(queries, qo, found, stream=s)
+    torch.cuda.synchronize()
+    graph_ms = timed(g.replay, reps)
+    ok = ok and int((out == cpht.PUT).sum().item()) + int((out == cpht.FULL).sum().item()) == total_k
+
+    views = [m.table(i) for i in range(n_tables)]
+    kb, qb = ko.tolist(), qo.tolist()
+
+    def per_table():
+        for i, v in enumerate(views):
+            v.insert(keys[kb[i]:kb[i + 1]], out[kb[i]:kb[i + 1]])
+        for i, v in enumerate(views):
+            v.find(queries[qb[i]:qb[i + 1]], found[qb[i]:qb[i + 1]])
+
+    per_table()
+    sep_ms = timed(per_table, 2)
+    ok = ok and int((out == cpht.PUT).sum().item()) + int((out == cpht.FULL).sum().item()) == total_k
+    return {
+        "config": (f"{n_tables} compact iceberg tables, 2^e + 2^(e-3) slots with e uniform in {lo}..{hi}, 32-bit "
+                   f"keys; fill each to {load} ({total_k} inserts), then 2x capacity finds at 50% hit "
+                   f"({total_q} finds)"),
+        "check": "ok" if ok and abs(hit_frac - 0.5) < 0.01 else "FAILED",
+        "puts": n_put, "full": n_full, "hit_fraction": round(hit_frac, 4),
+        "table_set_mops": round(ops / set_ms / 1e3, 1), "table_set_ms": round(set_ms, 3),
+        "graph_mops": round(ops / graph_ms / 1e3, 1), "graph_ms": round(graph_ms, 3),
+        "separate_launches_mops": round(ops / sep_ms / 1e3, 1), "separate_launches_ms": round(sep_ms, 3),
+        "graph_vs_separate": round(sep_ms / graph_ms, 2),
+        "variant_groups": info["groups"], "arena_bytes": info["arena_bytes"],
+        "autotune_seconds": round(tune_s, 2), "autotuned": chosen, "autotune_candidates": tried,
+    }
+
+
 def ceilings(torch, cpht, dev, res):
     """Measured random-access rates: 128-byte line reads, 32-bit CAS, and a
     line read followed by a CAS into it, on a buffer the size of the compact
@@ -304,6 +412,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ceilings", action="store_true", help="skip the random-access ceiling probes")
     ap.add_argument("--no-iceberg", action="store_true", help="skip the iceberg sections")
+    ap.add_argument("--no-many", action="store_true", help="skip the many-table section")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -469,6 +578,9 @@ def main():
     if not args.no_iceberg:
         res["iceberg_static"] = iceberg_static(torch, cpht, synth, dev)
         res["iceberg_mixed"] = iceberg_mixed(torch, cpht, synth, dev)
+
+    if not args.no_many:
+        res["many_tables"] = many_tables(torch, cpht, synth, dev)
 
     if not args.no_ceilings:
         res["ceilings"] = ceilings(torch, cpht, dev, res)

@@ -83,6 +83,11 @@ typedef struct {
  * compact, seed 1. */
 void cpht_config_default(uint32_t scheme, cpht_config_t* cfg);
 
+/* Check a configuration without allocating anything: CPHT_OK if cpht_create
+ * would accept it, and the resolved configuration (subtile filled in) in
+ * *resolved when resolved != NULL.  Touches no device. */
+cpht_status_t cpht_config_check(const cpht_config_t* cfg, cpht_config_t* resolved);
+
 /* Create an empty table (synchronous: allocates and zeroes device memory).
  * Level x holds 2^log2_slots_x slots in buckets of bucket_x slots; each
  * bucket is bucket_x*slot_bits_x/8 contiguous bytes.  The stored remainder

@@ -61,6 +61,7 @@ _lib = None
 _VP, _U32, _U64, _I32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
 _SIGNATURES = {
     "cpht_config_default": (None, [_U32, ctypes.POINTER(Config)]),
+    "cpht_config_check": (_I32, [ctypes.POINTER(Config), ctypes.POINTER(Config)]),
     "cpht_create": (_I32, [ctypes.POINTER(Config), ctypes.POINTER(_VP)]),
     "cpht_destroy": (_I32, [_VP]),
     "cpht_get_config": (_I32, [_VP, ctypes.POINTER(Config)]),
@@ -126,6 +127,13 @@ def default_config(scheme: int) -> Config:
     c = Config()
     lib().cpht_config_default(scheme, ctypes.byref(c))
     return c
+
+
+def check_config(cfg: Config) -> Config | None:
+    """The resolved configuration if the library accepts `cfg`, else None
+    (no device memory is touched)."""
+    out = Config()
+    return out if lib().cpht_config_check(ctypes.byref(cfg), ctypes.byref(out)) == 0 else None
 
 
 def variants(scheme: int) -> list[dict]:

@@ -209,6 +209,14 @@ void cpht_config_default(uint32_t scheme, cpht_config_t* c) {
   }
 }
 
+cpht_status_t cpht_config_check(const cpht_config_t* cfg, cpht_config_t* resolved) {
+  if (!cfg) return CPHT_E_ARG;
+  cpht_table t{};
+  const cpht_status_t st = configure_table(&t, *cfg);
+  if (st == CPHT_OK && resolved) *resolved = t.cfg;
+  return st;
+}
+
 cpht_status_t cpht_create(const cpht_config_t* cfg, cpht_table_t* out) {
   if (!cfg || !out) return CPHT_E_ARG;
   *out = nullptr;
