@@ -47,7 +47,7 @@ SECTOR = 64  # write-back unit of a modified slot (measured: 68.7 B written per 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by the
 # copy-kernel calibration factors 2.0 / 1.0), profiles/cuckoo_c2_hbm_bytes.md.
 # Valid only for the kernel sources they were taken with (hash below).
-TRAFFIC = {"csrc_sha": "5ff1a2c144aea60e", "cuckoo_put": 25937430028, "cuckoo_find": 11034506323}
+TRAFFIC = {"csrc_sha": "139d9fcc5377f9aa", "cuckoo_put": 25741440408, "cuckoo_find": 11035049786}
 
 
 def csrc_sha() -> str:
