@@ -367,6 +367,116 @@ def many_tables(torch, cpht, synth, dev, n_tables=4096, lo=10, hi=20, load=0.85,
     }
 
 
+def iceberg_zipf(torch, cpht, synth, dev, log2_slots0=28, batch=1 << 20, n_batches=200):
+    """Dynamic operation under skew: 2^28 + 2^25 slots, mixed batches of
+    `batch` operations (half finds, half find-or-puts), keys Zipf(1.1) over
+    2^34 ranks mapped to 34-bit keys by a bijection, for inserts and finds
+    alike; the hottest key is about 10 % of all draws, so most inserts repeat
+    a key already present."""
+    w = 34
+    L0, L1 = log2_slots0, log2_slots0 - 3
+    rows = {}
+    t = cpht.Table(scheme=cpht.ICEBERG, key_bits=w, log2_slots0=L0, log2_slots1=L1, bucket0=32, bucket1=16,
+                   slot_bits0=16, slot_bits1=32, seed=19)
+    ops = (synth.uniform_below(0x2F, batch, 2, dev)).to(torch.uint8)
+    out = torch.empty(batch, dtype=torch.uint8, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(n_batches + 1)]
+    keys = [synth.zipf_keys(w, KEY_SEED + 5, 1.1, batch, 1000 + b, device=dev) for b in range(n_batches)]
+    torch.cuda.synchronize()
+    puts = torch.zeros((), dtype=torch.int64, device=dev)
+    ev[0].record()
+    for b in range(n_batches):
+        t.mixed(keys[b], ops, out)
+        ev[b + 1].record()
+        puts += (out == cpht.PUT).sum()
+    torch.cuda.synchronize()
+    lat = [ev[b].elapsed_time(ev[b + 1]) for b in range(n_batches)]
+    occ, cap = t.count()
+    ms = sum(lat)
+    rows = {"mops": round(n_batches * batch / ms / 1e3, 1),
+            "batch_latency_ms": {"p50": round(pct(lat, 50), 4), "p99": round(pct(lat, 99), 4)},
+            "puts": int(puts.item()), "fill_factor": round(occ / cap, 4),
+            "config": (f"iceberg 2^{L0} + 2^{L1} slots (16/32-bit), {w}-bit keys Zipf(1.1) over 2^34 ranks; "
+                       f"{n_batches} mixed batches of {batch} ops (50% find / 50% find-or-put)")}
+    del t, keys
+    return rows
+
+
+def serving(torch, cpht, synth, dev, n_req=4000, log2_slots0=32, prefill=0.5, seed=3):
+    """Serving loop over one resident compact iceberg table of 2^32 + 2^29
+    slots (16/32-bit, 40-bit keys), pre-filled to load 0.5.  Requests: sizes
+    lognormal (median 4096, sigma 2) clipped to 1..2^22; 70 % finds (half hits)
+    and 30 % inserts of fresh keys; host-resident (pinned) buffers.  Runs: all
+    requests at t = 0 (saturation), then Poisson arrivals at 50 % and 90 % of
+    the saturated request rate; the comparator is the same server with one
+    request per launch and one launch in flight (plain batched launches in
+    arrival order).  The table is emptied and pre-filled again before each run."""
+    import numpy as np
+
+    w = 40
+    L0, L1 = log2_slots0, log2_slots0 - 3
+    cap = (1 << L0) + (1 << L1)
+    n_pre = int(prefill * cap)
+    t = cpht.Table(scheme=cpht.ICEBERG, key_bits=w, log2_slots0=L0, log2_slots1=L1, bucket0=32, bucket1=16,
+                   slot_bits0=16, slot_bits1=32, seed=23)
+
+    def refill():
+        t.clear(23)
+        chunk = 1 << 28
+        for a in range(0, n_pre, chunk):
+            k = synth.distinct_keys(w, KEY_SEED + 7, a, min(chunk, n_pre - a), device=dev)
+            t.insert(k)
+            del k
+        torch.cuda.synchronize()
+
+    r = np.random.default_rng(seed)
+    sizes = np.clip(np.round(np.exp(r.normal(np.log(4096), 2.0, n_req))), 1, 1 << 22).astype(np.int64)
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    total = int(offsets[-1])
+    is_ins = synth.uniform_below(0x31, total, 10, dev) < 3
+    is_hit = synth.uniform_below(0x32, total, 2, dev) == 1
+    fresh_idx = n_pre + torch.cumsum(is_ins.to(torch.int64), 0)
+    hit_idx = synth.uniform_below(0x33, total, 1 << 30, dev) * n_pre >> 30
+    miss_idx = (1 << 39) + torch.arange(total, device=dev)
+    idx = torch.where(is_ins, fresh_idx, torch.where(is_hit, hit_idx, miss_idx))
+    keys = synth.feistel(w, KEY_SEED + 7, idx).cpu().pin_memory()
+    ops = is_ins.to(torch.uint8).cpu().pin_memory()
+    out = torch.zeros(total, dtype=torch.uint8).pin_memory()
+    del is_ins, is_hit, fresh_idx, hit_idx, miss_idx, idx
+
+    def run(arrival, **kw):
+        refill()
+        srv = cpht.Server(t, **kw)
+        lat, mk = srv.replay(arrival, offsets, keys, ops, out)
+        st = srv.stats()
+        srv.stop()
+        lat_ms = lat.astype(np.float64) / 1e6
+        return {"mops": round(total / (mk / 1e9) / 1e6, 1), "requests_per_s": round(n_req / (mk / 1e9), 0),
+                "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+                "makespan_ms": round(mk / 1e6, 2), "launches": st["launches"], "max_queue": st["max_queue"]}
+
+    cont = dict(max_inflight=4, coalesce=1, staging_keys=1 << 25, max_batch_keys=1 << 22)
+    plain = dict(max_inflight=1, coalesce=0, staging_keys=1 << 25, max_batch_keys=1 << 22)
+    res = {"config": (f"iceberg 2^{L0} + 2^{L1} slots (16/32-bit, {t.level_bytes(0) + t.level_bytes(1)} bytes), "
+                      f"{w}-bit keys, pre-filled to load {prefill}; {n_req} requests, {total} operations, sizes "
+                      f"lognormal(median 4096, sigma 2) in 1..2^22, 70% find / 30% insert, pinned host buffers"),
+           "requests": n_req, "operations": total}
+    zero = np.zeros(n_req, dtype=np.uint64)
+    res["saturated"] = run(zero, **cont)
+    res["saturated_plain"] = run(zero, **plain)
+    rate = res["saturated"]["requests_per_s"]
+    for frac in (0.5, 0.9):
+        gaps = r.exponential(1e9 / (frac * rate), n_req)
+        arrival = np.cumsum(gaps).astype(np.uint64)
+        res[f"poisson_{int(frac * 100)}"] = run(arrival, **cont)
+        res[f"poisson_{int(frac * 100)}_plain"] = run(arrival, **plain)
+    occ, cp = t.count()
+    res["fill_factor_end"] = round(occ / cp, 4)
+    del t
+    return res
+
+
 def ceilings(torch, cpht, dev, res):
     """Measured random-access rates: 128-byte line reads, 32-bit CAS, and a
     line read followed by a CAS into it, on a buffer the size of the compact
@@ -413,6 +523,7 @@ def main():
     ap.add_argument("--no-ceilings", action="store_true", help="skip the random-access ceiling probes")
     ap.add_argument("--no-iceberg", action="store_true", help="skip the iceberg sections")
     ap.add_argument("--no-many", action="store_true", help="skip the many-table section")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop section")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -579,8 +690,14 @@ def main():
         res["iceberg_static"] = iceberg_static(torch, cpht, synth, dev)
         res["iceberg_mixed"] = iceberg_mixed(torch, cpht, synth, dev)
 
+    if not args.no_iceberg:
+        res["iceberg_zipf"] = iceberg_zipf(torch, cpht, synth, dev)
+
     if not args.no_many:
         res["many_tables"] = many_tables(torch, cpht, synth, dev)
+
+    if not args.no_serving:
+        res["serving"] = serving(torch, cpht, synth, dev)
 
     if not args.no_ceilings:
         res["ceilings"] = ceilings(torch, cpht, dev, res)

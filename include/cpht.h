@@ -211,6 +211,65 @@ cpht_status_t cpht_multi_info(cpht_multi_t m, uint64_t* arena_bytes, uint32_t* n
 /* Synchronise the device, return and clear the set's error flags. */
 cpht_status_t cpht_multi_error(cpht_multi_t m, uint32_t* flags);
 
+/* ---- Serving loop: continuous batching over one resident iceberg table ------
+ * A server owns a device staging ring (staging_keys keys with their opcodes and
+ * results) and max_inflight streams.  Its dispatcher thread admits queued
+ * requests in arrival order whenever a stream is free and the ring has room
+ * (admission by free device memory), packs the admitted requests (up to
+ * max_batch_keys keys; one request per launch if coalesce = 0) into one
+ * cpht_mixed launch, copies each request's results back, and completes the
+ * requests when that launch's event fires.  Requests arriving while earlier
+ * launches run are admitted into the next free stream, so launches overlap on
+ * the device; all of them operate on the same table concurrently (the dynamic
+ * operation of Sec. 3).  A find whose key another in-flight request inserts
+ * may therefore answer either way; every other answer equals the answer the
+ * request gets alone.  Host buffers passed to the server should be pinned
+ * (page-locked) for asynchronous copies and must stay valid until the request
+ * completes.  Latency = completion time - submission time (steady clock). */
+typedef struct cpht_server* cpht_server_t;
+
+typedef struct {
+    uint32_t max_inflight;    /* concurrent launches (streams), 1..64 */
+    uint32_t coalesce;        /* 1: pack several requests per launch; 0: one request per launch */
+    uint64_t staging_keys;    /* device staging capacity in keys (a request must fit it) */
+    uint64_t max_batch_keys;  /* keys per launch when coalescing (<= staging_keys) */
+} cpht_server_config_t;
+
+/* Defaults: 4 launches in flight, coalescing, 2^24 staging keys, 2^22 keys per launch. */
+void cpht_server_config_default(cpht_server_config_t* cfg);
+
+/* Start a server on an iceberg table (CPHT_E_STATE for cuckoo: static). */
+cpht_status_t cpht_server_start(cpht_table_t t, const cpht_server_config_t* cfg, cpht_server_t* out);
+
+/* Queue a request of n operations (h_ops[i]: CPHT_OP_FIND or CPHT_OP_INSERT);
+ * results go to h_out (find 0/1, insert PUT/FOUND/FULL).  Returns a ticket.
+ * CPHT_E_BUSY if 2^20 requests are already queued; CPHT_E_ARG if n exceeds
+ * the staging capacity. */
+cpht_status_t cpht_server_submit(cpht_server_t s, const void* h_keys, const uint8_t* h_ops, uint64_t n,
+                                 uint8_t* h_out, uint64_t* ticket);
+
+/* Non-blocking completion check; latency in ns once done. */
+cpht_status_t cpht_server_poll(cpht_server_t s, uint64_t ticket, int* done, uint64_t* latency_ns);
+
+/* Block until the request completes. */
+cpht_status_t cpht_server_wait(cpht_server_t s, uint64_t ticket, uint64_t* latency_ns);
+
+/* Launches issued, requests and operations completed, longest queue seen. */
+cpht_status_t cpht_server_stats(cpht_server_t s, uint64_t* launches, uint64_t* requests_done, uint64_t* ops_done,
+                                uint64_t* max_queue);
+
+/* Drain queued and in-flight requests, stop the dispatcher, free the server. */
+cpht_status_t cpht_server_stop(cpht_server_t s);
+
+/* Replay a request trace from the calling thread: request i (operations
+ * [offsets[i], offsets[i+1]) of h_keys / h_ops / h_out) is submitted
+ * arrival_ns[i] after the start (non-decreasing), then all are awaited.
+ * latency_ns[i] receives each request's latency; *makespan_ns the time from
+ * the start to the last completion. */
+cpht_status_t cpht_server_replay(cpht_server_t s, uint64_t n_requests, const uint64_t* arrival_ns,
+                                 const uint64_t* offsets, const void* h_keys, const uint8_t* h_ops, uint8_t* h_out,
+                                 uint64_t* latency_ns, uint64_t* makespan_ns);
+
 /* Measurement kernels for the random-access roofline (not table operations).
  * d_buf: device buffer of `bytes` bytes (a power of two, >= 4096), which the
  * CAS kinds modify; d_sink: one device word the kernels may write.

@@ -77,6 +77,15 @@ _SIGNATURES = {
     "cpht_split": (_I32, [_VP, _U32, _VP, _U64, _VP, _VP, _VP]),
     "cpht_variant_info": (_I32, [_U32, _I32, ctypes.POINTER(_U32)]),
     "cpht_probe": (_I32, [_U32, _VP, _U64, _U64, _U64, _VP, ctypes.POINTER(_U64), _VP]),
+    "cpht_server_config_default": (None, [_VP]),
+    "cpht_server_start": (_I32, [_VP, _VP, ctypes.POINTER(_VP)]),
+    "cpht_server_submit": (_I32, [_VP, _VP, _VP, _U64, _VP, ctypes.POINTER(_U64)]),
+    "cpht_server_poll": (_I32, [_VP, _U64, ctypes.POINTER(_I32), ctypes.POINTER(_U64)]),
+    "cpht_server_wait": (_I32, [_VP, _U64, ctypes.POINTER(_U64)]),
+    "cpht_server_stats": (_I32, [_VP, ctypes.POINTER(_U64), ctypes.POINTER(_U64), ctypes.POINTER(_U64),
+                                 ctypes.POINTER(_U64)]),
+    "cpht_server_stop": (_I32, [_VP]),
+    "cpht_server_replay": (_I32, [_VP, _U64, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(_U64)]),
     "cpht_multi_create": (_I32, [_U32, _VP, _U64, ctypes.POINTER(_VP)]),
     "cpht_multi_destroy": (_I32, [_VP]),
     "cpht_multi_table": (_I32, [_VP, _U32, ctypes.POINTER(_VP)]),
@@ -356,3 +365,89 @@ class MultiTable:
         f = _U32(0)
         _check(lib().cpht_multi_error(self._h, ctypes.byref(f)), "cpht_multi_error")
         return f.value
+
+
+class ServerConfig(ctypes.Structure):
+    """Mirror of cpht_server_config_t."""
+
+    _fields_ = [
+        ("max_inflight", ctypes.c_uint32),
+        ("coalesce", ctypes.c_uint32),
+        ("staging_keys", ctypes.c_uint64),
+        ("max_batch_keys", ctypes.c_uint64),
+    ]
+
+
+def _host_ptr(t, name: str) -> int:
+    if t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous host tensor (pinned for asynchronous copies)")
+    return t.data_ptr()
+
+
+class Server:
+    """Continuous-batching request loop over one iceberg table (cpht_server_t).
+    Request buffers are host tensors (pinned: tensor.pin_memory()) that must
+    stay alive until the request completes."""
+
+    def __init__(self, table: Table, **fields):
+        cfg = ServerConfig()
+        lib().cpht_server_config_default(ctypes.byref(cfg))
+        for k, v in fields.items():
+            setattr(cfg, k, int(v))
+        h = _VP()
+        _check(lib().cpht_server_start(table._h, ctypes.byref(cfg), ctypes.byref(h)), "cpht_server_start")
+        self._h, self._table, self.config = h, table, cfg
+        self._keep = {}
+
+    def submit(self, keys, ops, out) -> int:
+        if keys.dtype != self._table.key_dtype:
+            raise ValueError(f"keys must be {self._table.key_dtype}")
+        n = keys.numel()
+        if ops.numel() != n or out.numel() < n or ops.dtype != torch.uint8 or out.dtype != torch.uint8:
+            raise ValueError("ops and out must be uint8 with one entry per key")
+        tk = _U64(0)
+        _check(lib().cpht_server_submit(self._h, _host_ptr(keys, "keys"), _host_ptr(ops, "ops"), n,
+                                        _host_ptr(out, "out"), ctypes.byref(tk)), "cpht_server_submit")
+        self._keep[tk.value] = (keys, ops, out)
+        return tk.value
+
+    def poll(self, ticket: int):
+        d, lat = _I32(0), _U64(0)
+        _check(lib().cpht_server_poll(self._h, ticket, ctypes.byref(d), ctypes.byref(lat)), "cpht_server_poll")
+        return bool(d.value), lat.value
+
+    def wait(self, ticket: int) -> int:
+        lat = _U64(0)
+        _check(lib().cpht_server_wait(self._h, ticket, ctypes.byref(lat)), "cpht_server_wait")
+        self._keep.pop(ticket, None)
+        return lat.value
+
+    def stats(self) -> dict:
+        v = [_U64(0) for _ in range(4)]
+        _check(lib().cpht_server_stats(self._h, *[ctypes.byref(x) for x in v]), "cpht_server_stats")
+        return dict(zip(("launches", "requests_done", "ops_done", "max_queue"), (x.value for x in v)))
+
+    def replay(self, arrival_ns, offsets, keys, ops, out):
+        """Replay a trace (see cpht_server_replay); returns (latency_ns array, makespan_ns)."""
+        import numpy as np
+
+        arr = np.ascontiguousarray(np.asarray(arrival_ns, dtype=np.uint64))
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+        lat = np.zeros(arr.size, dtype=np.uint64)
+        mk = _U64(0)
+        _check(lib().cpht_server_replay(self._h, arr.size, arr.ctypes.data_as(_VP), off.ctypes.data_as(_VP),
+                                        _host_ptr(keys, "keys"), _host_ptr(ops, "ops"), _host_ptr(out, "out"),
+                                        lat.ctypes.data_as(_VP), ctypes.byref(mk)), "cpht_server_replay")
+        return lat, mk.value
+
+    def stop(self):
+        if getattr(self, "_h", None):
+            h, self._h = self._h, None
+            _check(lib().cpht_server_stop(h), "cpht_server_stop")
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass

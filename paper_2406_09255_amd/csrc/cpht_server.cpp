@@ -1,0 +1,379 @@
+// Serving loop over one resident iceberg table: continuous batching of mixed
+// find / find-or-put requests (C-ABI cpht_server_*, declared in cpht.h).
+//
+// A dispatcher thread owns all device work.  Submitted requests wait in a
+// FIFO queue; whenever a launch slot (stream) is free and the device staging
+// ring has room, the dispatcher admits the queued requests that fit (in
+// arrival order, up to max_batch_keys keys), copies their keys and opcodes
+// into consecutive staging space, runs one mixed find / find-or-put launch
+// over all of them, copies every request's results back, and records an
+// event.  Requests that arrive while earlier launches are on the device are
+// admitted into the next free slot, so up to max_inflight launches overlap.
+// Completed launches free their staging space and complete their requests.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "cpht.h"
+#include "cpht_internal.hpp"
+
+using namespace cpht;
+
+namespace {
+
+uint64_t now_ns() {
+  return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+struct Request {
+  const void* keys;
+  const uint8_t* ops;
+  uint8_t* out;
+  uint64_t n;
+  uint64_t t_submit;
+  uint64_t t_done;  // 0 while pending
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  bool busy = false;
+  uint64_t ring_begin = 0, ring_len = 0;  // staging range (in keys)
+  std::vector<uint64_t> reqs;
+};
+
+}  // namespace
+
+struct cpht_server {
+  cpht_table* table;
+  cpht_server_config_t cfg;
+  uint32_t key_bytes;
+  // device staging ring, in keys: keys, opcodes and results of admitted requests
+  void* d_keys = nullptr;
+  uint8_t* d_ops = nullptr;
+  uint8_t* d_out = nullptr;
+  uint64_t ring_cap = 0;
+  uint64_t ring_head = 0;  // next free key position (monotone counter)
+  uint64_t ring_tail = 0;  // oldest key position still in use
+  std::deque<std::pair<uint64_t, bool>> ring_allocs;  // (end position, freed) in allocation order
+  std::vector<Slot> slots;
+
+  std::mutex mu;
+  std::condition_variable cv;
+  std::vector<Request> reqs;  // indexed by ticket
+  std::deque<uint64_t> queue;
+  bool stopping = false;
+  std::atomic<int> error{0};
+  std::thread worker;
+
+  // statistics
+  uint64_t launches = 0, ops_done = 0, reqs_done = 0, max_queue = 0;
+};
+
+namespace {
+
+// Reserve `len` contiguous keys of the ring; false if there is no room now.
+bool ring_reserve(cpht_server* s, uint64_t len, uint64_t* begin) {
+  if (s->ring_head == s->ring_tail) {  // empty: start the next lap at position 0
+    const uint64_t lap = (s->ring_head + s->ring_cap - 1) / s->ring_cap * s->ring_cap;
+    s->ring_head = s->ring_tail = lap;
+  }
+  const uint64_t used = s->ring_head - s->ring_tail;
+  const uint64_t pos = s->ring_head % s->ring_cap;
+  uint64_t skip = 0;
+  if (pos + len > s->ring_cap) skip = s->ring_cap - pos;  // do not wrap inside an allocation
+  if (used + skip + len > s->ring_cap) return false;
+  if (skip) {
+    s->ring_head += skip;
+    s->ring_allocs.emplace_back(s->ring_head, true);  // padding, free at once
+  }
+  *begin = s->ring_head;
+  s->ring_head += len;
+  s->ring_allocs.emplace_back(s->ring_head, false);
+  return true;
+}
+
+void ring_release(cpht_server* s, uint64_t end) {
+  for (auto& a : s->ring_allocs)
+    if (a.first == end && !a.second) { a.second = true; break; }
+  while (!s->ring_allocs.empty() && s->ring_allocs.front().second) {
+    s->ring_tail = s->ring_allocs.front().first;
+    s->ring_allocs.pop_front();
+  }
+}
+
+// Copies in, one mixed launch, copies out, completion event.  `group` holds
+// copies of the requests (the request table may grow while this runs).
+hipError_t launch_group(cpht_server* s, Slot& slot, uint64_t begin, const std::vector<Request>& group) {
+  const hipStream_t st = slot.stream;
+  const uint64_t pos = begin % s->ring_cap;
+  uint64_t off = 0;
+  hipError_t e = hipSuccess;
+  for (const Request& r : group) {
+    char* dk = static_cast<char*>(s->d_keys) + (pos + off) * s->key_bytes;
+    e = hipMemcpyAsync(dk, r.keys, r.n * s->key_bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->d_ops + pos + off, r.ops, r.n, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    off += r.n;
+  }
+  const cpht_status_t cs = cpht_mixed(s->table, static_cast<char*>(s->d_keys) + pos * s->key_bytes,
+                                      s->d_ops + pos, off, s->d_out + pos, st);
+  if (cs != CPHT_OK) return hipErrorLaunchFailure;
+  off = 0;
+  for (const Request& r : group) {
+    e = hipMemcpyAsync(r.out, s->d_out + pos + off, r.n, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    off += r.n;
+  }
+  return hipEventRecord(slot.done, st);
+}
+
+void dispatcher(cpht_server* s) {
+  if (hipSetDevice(s->table->device) != hipSuccess) {
+    s->error = 1;
+    return;
+  }
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    bool inflight = false;
+    // 1. complete finished launches
+    for (Slot& sl : s->slots) {
+      if (!sl.busy) continue;
+      lk.unlock();
+      const hipError_t q = hipEventQuery(sl.done);
+      lk.lock();
+      if (q == hipErrorNotReady) {
+        inflight = true;
+        continue;
+      }
+      if (q != hipSuccess) s->error = 1;
+      const uint64_t t = now_ns();
+      for (uint64_t id : sl.reqs) {
+        s->reqs[id].t_done = t;
+        s->ops_done += s->reqs[id].n;
+        ++s->reqs_done;
+      }
+      ring_release(s, sl.ring_begin + sl.ring_len);
+      sl.busy = false;
+      sl.reqs.clear();
+      s->cv.notify_all();
+    }
+    // 2. admit queued requests into free slots while staging has room
+    for (Slot& sl : s->slots) {
+      if (sl.busy || s->queue.empty() || s->error) continue;
+      std::vector<uint64_t> ids;
+      uint64_t total = 0;
+      while (!s->queue.empty()) {
+        const uint64_t n = s->reqs[s->queue.front()].n;
+        if (!ids.empty() && (!s->cfg.coalesce || total + n > s->cfg.max_batch_keys)) break;
+        if (ids.empty() && n > s->cfg.max_batch_keys) {  // a request larger than one launch runs alone
+          ids.push_back(s->queue.front());
+          total = n;
+          break;
+        }
+        ids.push_back(s->queue.front());
+        total += n;
+        s->queue.pop_front();
+        if (!s->cfg.coalesce) break;
+      }
+      if (ids.size() == 1 && total > s->cfg.max_batch_keys) s->queue.pop_front();
+      uint64_t begin = 0;
+      if (!ring_reserve(s, total, &begin)) {  // no staging room: put them back, wait for completions
+        for (auto it = ids.rbegin(); it != ids.rend(); ++it) s->queue.push_front(*it);
+        break;
+      }
+      sl.busy = true;
+      sl.ring_begin = begin;
+      sl.ring_len = total;
+      sl.reqs = ids;
+      std::vector<Request> group;
+      group.reserve(ids.size());
+      for (uint64_t id : ids) group.push_back(s->reqs[id]);
+      lk.unlock();
+      const hipError_t e = launch_group(s, sl, begin, group);
+      lk.lock();
+      if (e != hipSuccess) s->error = 1;
+      ++s->launches;
+      inflight = true;
+    }
+    if (s->stopping && s->queue.empty() && !inflight) break;
+    if (s->error && !inflight) {
+      // fail everything still queued so waiters return
+      const uint64_t t = now_ns();
+      while (!s->queue.empty()) {
+        s->reqs[s->queue.front()].t_done = t;
+        s->queue.pop_front();
+      }
+      s->cv.notify_all();
+      if (s->stopping) break;
+    }
+    if (inflight) {
+      lk.unlock();
+      std::this_thread::yield();
+      lk.lock();
+    } else {
+      s->cv.wait_for(lk, std::chrono::microseconds(200));
+    }
+  }
+}
+
+void free_server(cpht_server* s) {
+  for (Slot& sl : s->slots) {
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+  }
+  if (s->d_keys) (void)hipFree(s->d_keys);
+  if (s->d_ops) (void)hipFree(s->d_ops);
+  if (s->d_out) (void)hipFree(s->d_out);
+  delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+void cpht_server_config_default(cpht_server_config_t* c) {
+  if (!c) return;
+  c->max_inflight = 4;
+  c->coalesce = 1;
+  c->staging_keys = 1ull << 24;
+  c->max_batch_keys = 1ull << 22;
+}
+
+cpht_status_t cpht_server_start(cpht_table_t t, const cpht_server_config_t* cfg, cpht_server_t* out) {
+  if (!t || !cfg || !out) return CPHT_E_ARG;
+  *out = nullptr;
+  if (!t->ice) return CPHT_E_STATE;  // the dynamic (iceberg) table only
+  if (cfg->max_inflight < 1 || cfg->max_inflight > 64 || cfg->staging_keys < 1 || cfg->max_batch_keys < 1 ||
+      cfg->max_batch_keys > cfg->staging_keys)
+    return CPHT_E_ARG;
+  cpht_server* s = new (std::nothrow) cpht_server();
+  if (!s) return CPHT_E_NOMEM;
+  s->table = t;
+  s->cfg = *cfg;
+  s->key_bytes = t->cfg.key_bits > 32 ? 8 : 4;
+  s->ring_cap = cfg->staging_keys;
+  DeviceGuard g(t->device);
+  hipError_t e = g.ok ? hipSuccess : hipErrorInvalidDevice;
+  if (e == hipSuccess) e = hipMalloc(&s->d_keys, s->ring_cap * s->key_bytes);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s->d_ops), s->ring_cap);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s->d_out), s->ring_cap);
+  s->slots.resize(cfg->max_inflight);
+  for (Slot& sl : s->slots) {
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    free_server(s);
+    return device_status(e);
+  }
+  s->worker = std::thread(dispatcher, s);
+  *out = s;
+  return CPHT_OK;
+}
+
+cpht_status_t cpht_server_submit(cpht_server_t s, const void* h_keys, const uint8_t* h_ops, uint64_t n,
+                                 uint8_t* h_out, uint64_t* ticket) {
+  if (!s || !ticket || (n && (!h_keys || !h_ops || !h_out))) return CPHT_E_ARG;
+  if (n > s->cfg.staging_keys) return CPHT_E_ARG;  // could never be admitted
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stopping) return CPHT_E_STATE;
+  if (s->error) return CPHT_E_DEVICE;
+  if (s->queue.size() >= (1u << 20)) return CPHT_E_BUSY;
+  Request r{h_keys, h_ops, h_out, n, now_ns(), 0};
+  *ticket = s->reqs.size();
+  s->reqs.push_back(r);
+  if (n == 0) {
+    s->reqs.back().t_done = r.t_submit;
+  } else {
+    s->queue.push_back(*ticket);
+    if (s->queue.size() > s->max_queue) s->max_queue = s->queue.size();
+  }
+  s->cv.notify_all();
+  return CPHT_OK;
+}
+
+cpht_status_t cpht_server_poll(cpht_server_t s, uint64_t ticket, int* done, uint64_t* latency_ns) {
+  if (!s || !done) return CPHT_E_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (ticket >= s->reqs.size()) return CPHT_E_ARG;
+  const Request& r = s->reqs[ticket];
+  *done = r.t_done != 0;
+  if (latency_ns) *latency_ns = r.t_done ? r.t_done - r.t_submit : 0;
+  return s->error ? CPHT_E_DEVICE : CPHT_OK;
+}
+
+cpht_status_t cpht_server_wait(cpht_server_t s, uint64_t ticket, uint64_t* latency_ns) {
+  if (!s) return CPHT_E_ARG;
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (ticket >= s->reqs.size()) return CPHT_E_ARG;
+  s->cv.wait(lk, [&] { return s->reqs[ticket].t_done != 0; });
+  if (latency_ns) *latency_ns = s->reqs[ticket].t_done - s->reqs[ticket].t_submit;
+  return s->error ? CPHT_E_DEVICE : CPHT_OK;
+}
+
+cpht_status_t cpht_server_stats(cpht_server_t s, uint64_t* launches, uint64_t* requests_done, uint64_t* ops_done,
+                                uint64_t* max_queue) {
+  if (!s) return CPHT_E_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (launches) *launches = s->launches;
+  if (requests_done) *requests_done = s->reqs_done;
+  if (ops_done) *ops_done = s->ops_done;
+  if (max_queue) *max_queue = s->max_queue;
+  return CPHT_OK;
+}
+
+cpht_status_t cpht_server_stop(cpht_server_t s) {
+  if (!s) return CPHT_E_ARG;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stopping = true;
+  }
+  s->cv.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  const int err = s->error;
+  DeviceGuard g(s->table->device);
+  free_server(s);
+  return err ? CPHT_E_DEVICE : CPHT_OK;
+}
+
+cpht_status_t cpht_server_replay(cpht_server_t s, uint64_t n_requests, const uint64_t* arrival_ns,
+                                 const uint64_t* offsets, const void* h_keys, const uint8_t* h_ops, uint8_t* h_out,
+                                 uint64_t* latency_ns, uint64_t* makespan_ns) {
+  if (!s || !arrival_ns || !offsets || !h_keys || !h_ops || !h_out || !latency_ns) return CPHT_E_ARG;
+  for (uint64_t i = 0; i < n_requests; ++i)
+    if (offsets[i + 1] < offsets[i] || (i && arrival_ns[i] < arrival_ns[i - 1])) return CPHT_E_ARG;
+  std::vector<uint64_t> tickets(n_requests);
+  const uint64_t t0 = now_ns();
+  for (uint64_t i = 0; i < n_requests; ++i) {
+    while (now_ns() - t0 < arrival_ns[i]) {  // wait for the request's arrival time
+      const uint64_t left = arrival_ns[i] - (now_ns() - t0);
+      if (left > 200000) std::this_thread::sleep_for(std::chrono::microseconds(100));
+    }
+    const char* k = static_cast<const char*>(h_keys) + offsets[i] * s->key_bytes;
+    cpht_status_t st;
+    while ((st = cpht_server_submit(s, k, h_ops + offsets[i], offsets[i + 1] - offsets[i], h_out + offsets[i],
+                                    &tickets[i])) == CPHT_E_BUSY)
+      std::this_thread::yield();
+    if (st != CPHT_OK) return st;
+  }
+  cpht_status_t worst = CPHT_OK;
+  for (uint64_t i = 0; i < n_requests; ++i) {
+    const cpht_status_t st = cpht_server_wait(s, tickets[i], &latency_ns[i]);
+    if (st != CPHT_OK) worst = st;
+  }
+  if (makespan_ns) *makespan_ns = now_ns() - t0;
+  return worst;
+}
+
+}  // extern "C"

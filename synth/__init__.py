@@ -134,6 +134,53 @@ def insert_stream_with_duplicates(w: int, key_seed: int, fresh_start: int, n_ops
     return feistel(w, key_seed, idx), n_fresh
 
 
+def zipf_ranks(s: float, n: int, count: int, seed: int, device="cpu") -> torch.Tensor:
+    """count i.i.d. draws from Zipf(s) on {1, ..., n} (P(k) proportional to
+    k^-s, s > 0, s != 1), by rejection-inversion (W. Hormann and G. Derflinger,
+    "Rejection-inversion to generate variates from monotone discrete
+    distributions", ACM TOMACS 6(3), 1996): invert the integral H of the
+    continuous hat x^-s over [k - 1/2, k + 1/2] and accept k unless the draw
+    falls in the gap between hat and histogram.  float64 arithmetic; the
+    uniform draws are counter-based (splitmix64 of seed and draw index)."""
+    if s <= 0 or s == 1.0:
+        raise ValueError("s must be positive and != 1")
+    f64 = torch.float64
+    q = 1.0 - s
+
+    def H(x):  # integral of t^-s from 1 to x
+        return torch.expm1(q * torch.log(x)) / q
+
+    def Hinv(y):
+        return torch.exp(torch.log1p(q * y) / q)
+
+    def h(x):
+        return torch.exp(-s * torch.log(x))
+
+    one = torch.tensor(1.0, dtype=f64, device=device)
+    hx1 = float(H(one * 1.5) - 1.0)
+    hn = float(H(one * (n + 0.5)))
+    sconst = float(2.0 - Hinv(H(one * 2.5) - h(one * 2.0)))
+    out = torch.zeros(count, dtype=torch.int64, device=device)
+    todo = torch.arange(count, device=device)
+    rnd = 0
+    while todo.numel():
+        u01 = (_lsr(_rand_u64(seed + 0x1000 * rnd, 0, count, device)[todo], 11)).to(f64) * (1.0 / (1 << 53))
+        u = hn + u01 * (hx1 - hn)
+        x = Hinv(u)
+        k = torch.clamp(torch.floor(x + 0.5), 1, n)
+        ok = (k - x <= sconst) | (u >= H(k + 0.5) - h(k))
+        out[todo[ok]] = k[ok].to(torch.int64)
+        todo = todo[~ok]
+        rnd += 1
+    return out
+
+
+def zipf_keys(w: int, key_seed: int, s: float, count: int, seed: int, device="cpu") -> torch.Tensor:
+    """Zipf(s) draws over ranks 1..2^w mapped to w-bit keys by the Feistel
+    bijection: key = phi(rank - 1)."""
+    return feistel(w, key_seed, zipf_ranks(s, 1 << w, count, seed, device) - 1)
+
+
 def to_words(keys: torch.Tensor, w: int) -> torch.Tensor:
     """Key words as stored for the library: int32 lanes (bit pattern of a
     uint32) when w <= 32, int64 lanes otherwise."""

@@ -67,3 +67,31 @@ def test_word_conversion_round_trip():
     wds = synth.to_words(k, 32)
     assert wds.dtype == torch.int32
     assert torch.equal(synth.from_words(wds), k)
+
+
+@pytest.mark.parametrize("s,n", [(1.1, 100), (1.5, 1000), (0.8, 50)])
+def test_zipf_matches_exact_pmf(s, n):
+    """Chi-square of 400k draws against the exact pmf k^-s / sum_j j^-s."""
+    draws = synth.zipf_ranks(s, n, 400000, 17)
+    assert int(draws.min()) >= 1 and int(draws.max()) <= n
+    counts = torch.bincount(draws, minlength=n + 1)[1:].double().numpy()
+    k = np.arange(1, n + 1, dtype=np.float64)
+    p = k ** -s / (k ** -s).sum()
+    exp = p * draws.numel()
+    keep = exp >= 5
+    chi2 = (((counts - exp) ** 2) / exp)[keep].sum() + 0.0
+    dof = keep.sum() - 1
+    assert abs(chi2 - dof) < 6 * np.sqrt(2 * dof), (chi2, dof)
+
+
+def test_zipf_head_share_large_domain():
+    """Over 2^34 ranks with s = 1.1 the top rank holds 1/zeta-like share:
+    P(1) = 1 / sum_{k<=2^34} k^-1.1 (about 0.104)."""
+    draws = synth.zipf_ranks(1.1, 1 << 34, 200000, 3)
+    share = float((draws == 1).double().mean())
+    # sum_{k=1}^{N} k^-s ~ zeta(s) - N^(1-s)/(s-1) (Euler-Maclaurin, first terms)
+    from scipy.special import zeta
+
+    N = float(1 << 34)
+    norm = zeta(1.1) - N ** (-0.1) / 0.1 + 0.5 * N ** -1.1
+    assert abs(share - 1.0 / norm) < 0.004, share
