@@ -701,6 +701,14 @@ def main():
 
     if not args.no_ceilings:
         res["ceilings"] = ceilings(torch, cpht, dev, res)
+        c = res["ceilings"]["table_size"]
+        if res["roofline"]["kernel"] == "cuckoo_put":
+            # one CAS per put round: the device's random line-read-then-CAS rate bounds the kernel
+            res["roofline"]["atomic_ceiling"] = {
+                "what": "measured random 128-B line read + 32-bit CAS into it, table-sized buffer",
+                "G_per_s": c["line_read_then_cas"]["G_per_s"],
+                "achieved_G_per_s": round(res["insert_mops"] * ROUNDS_PER_PUT[LOAD] / 1e3, 2),
+                "frac": res["ceilings"]["put_vs_line_read_then_cas"]}
 
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline()

@@ -1,0 +1,34 @@
+"""bench.py on the host: the multi-GPU request is refused with a message, and
+the pieces of the roofline arithmetic behave as documented."""
+import subprocess
+import sys
+import os
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_algorithmic_bytes_model():
+    # one round: a 128-byte bucket read, a 64-byte write-back, key and result bytes
+    assert abs(bench.put_bytes(0.5, 1) - (1.00002 * 192 + 9)) < 1e-9
+    assert abs(bench.find_bytes(0.9, 2) - (1.22454 * 256 + 9)) < 1e-9
+
+
+def test_traffic_is_tied_to_kernel_sources():
+    sha = bench.csrc_sha()
+    assert len(sha) == 16 and all(c in "0123456789abcdef" for c in sha)
+
+
+def test_percentiles():
+    xs = list(range(1, 101))
+    assert bench.pct(xs, 50) in (50, 51)
+    assert bench.pct(xs, 99) == 99
