@@ -114,27 +114,48 @@ void ring_release(cpht_server* s, uint64_t end) {
 
 // Copies in, one mixed launch, copies out, completion event.  `group` holds
 // copies of the requests (the request table may grow while this runs).
+// Requests whose host buffers follow each other directly (as in a trace laid
+// out in arrival order) share one copy per buffer, so the number of copies
+// grows with the number of separate host regions, not of requests.
 hipError_t launch_group(cpht_server* s, Slot& slot, uint64_t begin, const std::vector<Request>& group) {
   const hipStream_t st = slot.stream;
   const uint64_t pos = begin % s->ring_cap;
-  uint64_t off = 0;
+  const uint64_t kb = s->key_bytes;
   hipError_t e = hipSuccess;
-  for (const Request& r : group) {
-    char* dk = static_cast<char*>(s->d_keys) + (pos + off) * s->key_bytes;
-    e = hipMemcpyAsync(dk, r.keys, r.n * s->key_bytes, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(s->d_ops + pos + off, r.ops, r.n, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return e;
-    off += r.n;
+  uint64_t off = 0;
+  for (size_t i = 0; i < group.size() && e == hipSuccess;) {
+    // extend a run of requests adjacent in all three host buffers
+    size_t j = i + 1;
+    uint64_t n = group[i].n;
+    while (j < group.size() &&
+           static_cast<const char*>(group[j].keys) == static_cast<const char*>(group[i].keys) + n * kb &&
+           group[j].ops == group[i].ops + n && group[j].out == group[i].out + n) {
+      n += group[j].n;
+      ++j;
+    }
+    char* dk = static_cast<char*>(s->d_keys) + (pos + off) * kb;
+    e = hipMemcpyAsync(dk, group[i].keys, n * kb, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->d_ops + pos + off, group[i].ops, n, hipMemcpyHostToDevice, st);
+    off += n;
+    i = j;
   }
-  const cpht_status_t cs = cpht_mixed(s->table, static_cast<char*>(s->d_keys) + pos * s->key_bytes,
-                                      s->d_ops + pos, off, s->d_out + pos, st);
+  if (e != hipSuccess) return e;
+  const cpht_status_t cs = cpht_mixed(s->table, static_cast<char*>(s->d_keys) + pos * kb, s->d_ops + pos, off,
+                                      s->d_out + pos, st);
   if (cs != CPHT_OK) return hipErrorLaunchFailure;
   off = 0;
-  for (const Request& r : group) {
-    e = hipMemcpyAsync(r.out, s->d_out + pos + off, r.n, hipMemcpyDeviceToHost, st);
-    if (e != hipSuccess) return e;
-    off += r.n;
+  for (size_t i = 0; i < group.size() && e == hipSuccess;) {
+    size_t j = i + 1;
+    uint64_t n = group[i].n;
+    while (j < group.size() && group[j].out == group[i].out + n) {
+      n += group[j].n;
+      ++j;
+    }
+    e = hipMemcpyAsync(group[i].out, s->d_out + pos + off, n, hipMemcpyDeviceToHost, st);
+    off += n;
+    i = j;
   }
+  if (e != hipSuccess) return e;
   return hipEventRecord(slot.done, st);
 }
 
