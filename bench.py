@@ -46,18 +46,21 @@ SECTOR = 64  # write-back unit of a modified slot (measured: 68.7 B written per 
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by the
 # copy-kernel calibration factors 2.0 / 1.0), profiles/cuckoo_c2_hbm_bytes.md.
-# Valid only for the kernel sources they were taken with (hash below).
-TRAFFIC = {"csrc_sha": "139d9fcc5377f9aa", "cuckoo_put": 25741440408, "cuckoo_find": 11035049786}
+# Valid only for the kernel sources they were taken with (hash of KERNEL_SOURCES below).
+TRAFFIC = {"csrc_sha": "87b77f4d5da3721a", "cuckoo_put": 25741440408, "cuckoo_find": 11035049786}
+
+
+# The sources the profiled cuckoo kernels are compiled from.
+KERNEL_SOURCES = ("cpht_device.hpp", "cpht_cuckoo.hpp", "cpht_registry.hpp", "inst_cuckoo_u64.hip")
 
 
 def csrc_sha() -> str:
-    import glob
     import hashlib
 
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2406_09255_amd", "csrc", "*"))):
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
+    for name in KERNEL_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(ROOT, "paper_2406_09255_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
