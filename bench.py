@@ -151,6 +151,40 @@ def cpu_baseline(log2_slots: int = 25):
     }
 
 
+def small_cuckoo(torch, cpht, synth, dev, reps=20):
+    """The small cuckoo shape: 2^17 slots in 2^12 buckets of 32 x 32-bit
+    slots, 32-bit keys split into a 12-bit bucket and a 20-bit remainder plus
+    the hash-index bit; bulk insert 104,857 keys (load 0.8), then 10^5 finds
+    with 50 % hits.  The table (512 KiB) lives in cache, so this measures the
+    latency of one small batch (launch included), not bandwidth."""
+    w, L, n, nq = 32, 17, 104857, 100000
+    t = cpht.Table(scheme=cpht.CUCKOO, key_bits=w, log2_slots0=L, bucket0=32, slot_bits0=32, seed=1)
+    keys = synth.to_words(synth.distinct_keys(w, KEY_SEED + 11, 0, n, device=dev), w)
+    q = synth.to_words(synth.find_queries(w, KEY_SEED + 11, n, nq, 0.5, Q_SEED, device=dev), w)
+    out = torch.empty(n, dtype=torch.uint8, device=dev)
+    found = torch.empty(nq, dtype=torch.uint8, device=dev)
+    ins, fnd = [], []
+    for r in range(reps + 2):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        t.clear(100 + r)
+        e[0].record()
+        t.bulk_build(keys, out)
+        e[1].record()
+        t.find(q, found)
+        e[2].record()
+        e[2].synchronize()
+        if r >= 2:
+            ins.append(e[0].elapsed_time(e[1]) * 1000)
+            fnd.append(e[1].elapsed_time(e[2]) * 1000)
+    ok = int((out == cpht.PUT).sum().item()) == n and abs(float(found.float().mean().item()) - 0.5) < 0.01
+    return {"config": "cuckoo H=2, 2^17 slots in 2^12 buckets of 32 x 32-bit slots, 32-bit keys; insert 104857 "
+                      "(load 0.8) then 10^5 finds 50% hit",
+            "check": "ok" if ok else "FAILED",
+            "insert_us": {"p50": round(pct(ins, 50), 2), "p99": round(pct(ins, 99), 2)},
+            "find_us": {"p50": round(pct(fnd, 50), 2), "p99": round(pct(fnd, 99), 2)},
+            "insert_mops": round(n / pct(ins, 50), 1), "find_mops": round(nq / pct(fnd, 50), 1)}
+
+
 def iceberg_static(torch, cpht, synth, dev, reps=3):
     """Iceberg Put / Find at the paper's Sec. 5.1 shape: 2^27 primary + 2^24
     secondary slots, B0 = 32, B1 = 16, 37-bit keys; fill from empty to load
@@ -688,6 +722,8 @@ def main():
                               "full": full})
             del t, r
         res["sweep"] = sweep
+
+    res["small_cuckoo"] = small_cuckoo(torch, cpht, synth, dev)
 
     if not args.no_iceberg:
         res["iceberg_static"] = iceberg_static(torch, cpht, synth, dev)

@@ -1,0 +1,108 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times.  Expected answers come from the plain definition, made cheap by how
+the inputs are built: keys phi(i < n) are inserted, phi(i >= n) never are, so
+every find's answer is fixed by the index it was drawn from; the full
+2^27-slot cuckoo table is also run through the oracle's table checker."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2406_09255_amd as cpht
+import synth
+from tests.helpers import oracle_cfg
+
+pytestmark = pytest.mark.gpu
+
+SEED = 0xF0F0
+
+
+def _queries(w, n, nq, seed, dev):
+    """nq queries, half hits phi(i < n), half misses phi(i >= n), with the truth."""
+    hit = synth.uniform_below(seed, nq, 2, dev) == 1
+    hidx = synth.uniform_below(seed + 1, nq, 1 << 30, dev) * n >> 30
+    midx = n + torch.arange(nq, device=dev)
+    idx = torch.where(hit, hidx, midx)
+    return synth.feistel(w, SEED, idx), hit.to(torch.uint8)
+
+
+def test_c2_compact_cuckoo_full_size(gpu):
+    """2^27 slots, 32 x 32-bit buckets, 37-bit keys, load 0.9, 2^26 finds."""
+    w, L = 37, 27
+    n = int(0.9 * (1 << L))
+    t = cpht.Table(scheme=cpht.CUCKOO, key_bits=w, log2_slots0=L, bucket0=32, slot_bits0=32, seed=77)
+    keys = synth.distinct_keys(w, SEED, 0, n, device=gpu)
+    out = t.bulk_build(keys)
+    assert int((out == cpht.PUT).sum().item()) == n
+    assert t.count() == (n, 1 << L)
+    q, truth = _queries(w, n, 1 << 26, 5, gpu)
+    f = t.find(q)
+    assert torch.equal(f, truth)
+    ok, msg, dec = oracle.check_images(oracle_cfg(t), t.export(0))
+    assert ok, msg
+    assert dec.size == n
+    # the decoded set is exactly the inserted set: compare sorted arrays
+    want = np.sort(keys.cpu().numpy().astype(np.uint64))
+    assert np.array_equal(dec, want)
+
+
+def test_c2_plain_cuckoo_full_size(gpu):
+    w, L = 37, 27
+    n = int(0.9 * (1 << L))
+    t = cpht.Table(scheme=cpht.CUCKOO, key_bits=w, log2_slots0=L, bucket0=32, slot_bits0=64, compact=0, seed=78)
+    keys = synth.distinct_keys(w, SEED, 0, n, device=gpu)
+    out = t.bulk_build(keys)
+    assert int((out == cpht.PUT).sum().item()) == n
+    q, truth = _queries(w, n, 1 << 26, 6, gpu)
+    assert torch.equal(t.find(q), truth)
+
+
+def test_c3_iceberg_full_size_batches(gpu):
+    """2^28 + 2^25 slots, 16/32-bit, 34-bit keys, filled to load 0.85 in
+    batches of 2^20 with 30 % duplicate inserts: one PUT per distinct key,
+    the count equals the distinct keys, every inserted key is found and
+    2^24 never-inserted keys are not."""
+    w, L0 = 34, 28
+    cap = (1 << L0) + (1 << (L0 - 3))
+    t = cpht.Table(scheme=cpht.ICEBERG, key_bits=w, log2_slots0=L0, log2_slots1=L0 - 3, bucket0=32, bucket1=16,
+                   slot_bits0=16, slot_bits1=32, seed=79)
+    target = int(0.85 * cap)
+    batch = 1 << 20
+    issued, puts, full, b = 0, 0, 0, 0
+    out = torch.empty(batch, dtype=torch.uint8, device=gpu)
+    while issued < target:
+        keys, nf = synth.insert_stream_with_duplicates(w, SEED, issued, batch, 0.3, 1000 + b, device=gpu)
+        t.insert(keys, out)
+        puts += int((out == cpht.PUT).sum().item())
+        full += int((out == cpht.FULL).sum().item())
+        issued += nf
+        b += 1
+    assert full == 0
+    assert puts == issued
+    assert t.count()[0] == issued
+    for a in range(0, issued, 1 << 26):
+        k = synth.distinct_keys(w, SEED, a, min(1 << 26, issued - a), device=gpu)
+        assert bool((t.find(k) == 1).all().item())
+    miss = synth.distinct_keys(w, SEED, 1 << 33, 1 << 24, device=gpu)
+    assert int(t.find(miss).sum().item()) == 0
+
+
+def test_c5_table_shape_full_size(gpu):
+    """The serving table: 2^32 + 2^29 slots (16/32-bit, 40-bit keys), bulk
+    filled to load 0.5 in chunks; count and sampled finds are exact."""
+    w, L0 = 40, 32
+    cap = (1 << L0) + (1 << (L0 - 3))
+    t = cpht.Table(scheme=cpht.ICEBERG, key_bits=w, log2_slots0=L0, log2_slots1=L0 - 3, bucket0=32, bucket1=16,
+                   slot_bits0=16, slot_bits1=32, seed=80)
+    n = int(0.5 * cap)
+    chunk = 1 << 28
+    puts = 0
+    for a in range(0, n, chunk):
+        k = synth.distinct_keys(w, SEED, a, min(chunk, n - a), device=gpu)
+        puts += int((t.insert(k) == cpht.PUT).sum().item())
+        del k
+    assert puts == n and t.count() == (n, cap)
+    q, truth = _queries(w, n, 1 << 24, 7, gpu)
+    assert torch.equal(t.find(q), truth)
