@@ -114,7 +114,133 @@ class Runner:
         return ins, fnd
 
 
-def cpu_baseline(log2_slots: int = 25):
+# (slot bits, compact, slots per bucket) of the load sweep: compact 32-bit and
+# plain 64-bit slots at 8, 16 and 32 slots per bucket.
+SWEEP_SHAPES = ((32, 1, 32), (64, 0, 32), (32, 1, 16), (64, 0, 16), (32, 1, 8), (64, 0, 8))
+
+
+def equal_memory(torch, cpht, keys, queries, n_ins, reps=5):
+    """Equal memory, equal key count: the compact table gets 2^28 32-bit slots
+    (1 GiB, the plain table's footprint) and the same 0.9 * 2^27 keys, so it
+    runs at load 0.45 while the plain 2^27 x 64-bit table runs at 0.9."""
+    L = LOG2_SLOTS + 1
+    t = cpht.Table(scheme=cpht.CUCKOO, key_bits=W_KEY, log2_slots0=L, bucket0=BUCKET, slot_bits0=32,
+                   n_hash=2, max_chain=256, compact=1, seed=1)
+    r = Runner(torch, cpht, t, keys, queries, n_ins)
+    for rep in range(reps + 1):
+        r.step(seed=300 + rep, record=rep > 0)
+    ins, fnd = r.times_ms()
+    ok = int((r.out[:n_ins] == cpht.PUT).sum().item()) == n_ins
+    res = {"config": (f"compact cuckoo 2^{L} slots x 32-bit ({t.level_bytes(0)} bytes) holding the same {n_ins} keys "
+                      f"(load {n_ins / (1 << L):.3f}), 2^26 finds 50% hit"),
+           "check": "ok" if ok else "FAILED", "table_bytes": t.level_bytes(0),
+           "insert_mops": round(n_ins / (sum(ins) / len(ins) / 1000.0) / 1e6, 1),
+           "find_mops": round(N_FIND / (sum(fnd) / len(fnd) / 1000.0) / 1e6, 1)}
+    del t, r
+    return res
+
+
+def marginal_window(torch, cpht, keys, n_ins, lo=0.85, reps=5):
+    """Insert throughput of the last window of the build: fill the compact
+    table to load `lo` (untimed), then time inserting the keys that take it
+    from `lo` to 0.9."""
+    n_lo = int(lo * (1 << LOG2_SLOTS))
+    t = cpht.Table(scheme=cpht.CUCKOO, key_bits=W_KEY, log2_slots0=LOG2_SLOTS, bucket0=BUCKET, slot_bits0=32,
+                   n_hash=2, max_chain=256, compact=1, seed=1)
+    out = torch.empty(n_ins - n_lo, dtype=torch.uint8, device=keys.device)
+    times, ok = [], True
+    for rep in range(reps + 1):
+        t.clear(500 + rep)
+        t.insert(keys[:n_lo])
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        t.insert(keys[n_lo:n_ins], out)
+        b.record()
+        b.synchronize()
+        ok = ok and int((out == cpht.PUT).sum().item()) == out.numel()
+        if rep:
+            times.append(a.elapsed_time(b))
+    del t
+    return {"window": [lo, LOAD], "keys": n_ins - n_lo, "check": "ok" if ok else "FAILED",
+            "insert_mops": round((n_ins - n_lo) / (sum(times) / len(times) / 1000.0) / 1e6, 1),
+            "ms": round(sum(times) / len(times), 4)}
+
+
+def find_or_put(torch, cpht, synth, dev, reps=3):
+    """The find-or-put experiment: a table filled to a `before` load gets one
+    find-or-put batch with as many keys as it has slots -- stored keys, fresh
+    keys and repeats of both -- that fills it to exactly the `after` load.
+    Iceberg (2^27 + 2^24 slots) runs its own find-or-put; cuckoo (2^27 slots)
+    runs the sorted find-or-put (sort the batch, look each distinct key up
+    once, put the missing ones).  37-bit keys; the timed region is the one
+    call, keys resident; the table is rebuilt to `before` (untimed) each rep."""
+    w, L = 37, 27
+    shapes = [
+        ("iceberg_16_32", dict(scheme=cpht.ICEBERG, key_bits=w, log2_slots0=L, log2_slots1=L - 3, bucket0=32,
+                               bucket1=16, slot_bits0=16, slot_bits1=32, seed=5), ((0.0, 0.5), (0.5, 0.9), (0.8, 0.9))),
+        ("iceberg_64_64", dict(scheme=cpht.ICEBERG, key_bits=w, log2_slots0=L, log2_slots1=L - 3, bucket0=32,
+                               bucket1=16, slot_bits0=64, slot_bits1=64, compact=0, seed=5), ((0.5, 0.9),)),
+        ("cuckoo_32", dict(scheme=cpht.CUCKOO, key_bits=w, log2_slots0=L, bucket0=32, slot_bits0=32, seed=5),
+         ((0.0, 0.5), (0.5, 0.9), (0.8, 0.9))),
+        ("cuckoo_64", dict(scheme=cpht.CUCKOO, key_bits=w, log2_slots0=L, bucket0=32, slot_bits0=64, compact=0,
+                           seed=5), ((0.5, 0.9),)),
+    ]
+    res = {"config": "find-or-put batch of #slots keys (stored + fresh, with repeats) taking the table from the "
+                     "`before` to the `after` load; iceberg 2^27 + 2^24 slots, cuckoo 2^27 slots (sorted "
+                     "find-or-put), 37-bit keys"}
+    for name, kw, combos in shapes:
+        t = cpht.Table(**kw)
+        cap = t.count()[1]
+        ws = None
+        if kw["scheme"] == cpht.CUCKOO:
+            ws = torch.empty(t.sorted_fop_workspace(cap), dtype=torch.uint8, device=dev)
+        rows = []
+        for before, after in combos:
+            n_b, n_a = int(before * cap), int(after * cap)
+            pre = synth.distinct_keys(w, KEY_SEED + 3, 0, n_b, device=dev)
+            keys, idx = synth.find_or_put_batch(w, KEY_SEED + 3, n_b, n_a - n_b, cap, 41, device=dev)
+            del idx
+            out = torch.empty(cap, dtype=torch.uint8, device=dev)
+            times, ok = [], True
+            for rep in range(reps + 1):
+                t.clear(60 + rep)
+                if n_b:
+                    t.insert(pre)
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                if ws is not None:
+                    t.sorted_fop(keys, out, ws)
+                else:
+                    t.insert(keys, out)
+                b.record()
+                b.synchronize()
+                ok = ok and int((out == cpht.PUT).sum().item()) == n_a - n_b and t.count()[0] == n_a
+                if rep:
+                    times.append(a.elapsed_time(b))
+            ms = sum(times) / len(times)
+            rows.append({"before": before, "after": after, "ops": cap, "ms": round(ms, 3),
+                         "mops": round(cap / (ms / 1000.0) / 1e6, 1), "check": "ok" if ok else "FAILED"})
+            del pre, keys, out
+        res[name] = rows
+        del t, ws
+    m = {r["before"]: r["mops"] for r in res["iceberg_16_32"]}
+    c = {r["before"]: r["mops"] for r in res["cuckoo_32"]}
+    res["iceberg_vs_sorted_cuckoo"] = {str(k): round(m[k] / c[k], 2) for k in m if k in c}
+    return res
+
+
+def _host_cpu() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(log2_slots: int = 26):
     """The sequential oracle on the host: same bucket shape, load and find mix,
     at 2^log2_slots slots (a bounded sample of the workload)."""
     import numpy as np
@@ -148,6 +274,7 @@ def cpu_baseline(log2_slots: int = 25):
         "seconds": round(t2 - t0, 2),
         "hit_fraction": round(float(f.mean()), 4),
         "host_threads_available": os.cpu_count(),
+        "host_cpu": _host_cpu(),
     }
 
 
@@ -444,8 +571,8 @@ def serving(torch, cpht, synth, dev, n_req=4000, log2_slots0=32, prefill=0.5, se
     slots (16/32-bit, 40-bit keys), pre-filled to load 0.5.  Requests: sizes
     lognormal (median 4096, sigma 2) clipped to 1..2^22; 70 % finds (half hits)
     and 30 % inserts of fresh keys; host-resident (pinned) buffers.  Runs: all
-    requests at t = 0 (saturation), then Poisson arrivals at 50 % and 90 % of
-    the saturated request rate; the comparator is the same server with one
+    requests at t = 0 (saturation), then Poisson arrivals at 25, 50, 75 and 90 %
+    of the saturated request rate; the comparator is the same server with one
     request per launch and one launch in flight (plain batched launches in
     arrival order).  The table is emptied and pre-filled again before each run."""
     import numpy as np
@@ -503,7 +630,7 @@ def serving(torch, cpht, synth, dev, n_req=4000, log2_slots0=32, prefill=0.5, se
     res["saturated"] = run(zero, **cont)
     res["saturated_plain"] = run(zero, **plain)
     rate = res["saturated"]["requests_per_s"]
-    for frac in (0.5, 0.9):
+    for frac in (0.25, 0.5, 0.75, 0.9):
         gaps = r.exponential(1e9 / (frac * rate), n_req)
         arrival = np.cumsum(gaps).astype(np.uint64)
         res[f"poisson_{int(frac * 100)}"] = run(arrival, **cont)
@@ -699,28 +826,37 @@ def main():
         }
         del plain, prun
 
+    if not args.no_plain:
+        res["equal_memory"] = equal_memory(torch, cpht, keys, queries, n_ins)
+
+    res["marginal_window"] = marginal_window(torch, cpht, keys, n_ins)
+
     if not args.no_sweep:
+        loads = (0.5, 0.7, 0.8, 0.9, 0.95)
+        qs = {load: synth.find_queries(W_KEY, KEY_SEED, int(load * (1 << LOG2_SLOTS)), N_FIND, 0.5, Q_SEED + 7,
+                                       device=dev) for load in loads}
         sweep = []
-        for slot_bits, cmp_ in ((32, 1), (64, 0)):
+        for slot_bits, cmp_, bucket in SWEEP_SHAPES:
             if cmp_ == 0 and args.no_plain:
                 continue
-            t = cpht.Table(scheme=cpht.CUCKOO, key_bits=W_KEY, log2_slots0=LOG2_SLOTS, bucket0=BUCKET,
+            t = cpht.Table(scheme=cpht.CUCKOO, key_bits=W_KEY, log2_slots0=LOG2_SLOTS, bucket0=bucket,
                            slot_bits0=slot_bits, n_hash=2, max_chain=256, compact=cmp_, seed=1)
             r = Runner(torch, cpht, t, keys, queries, 0)
-            for load in (0.5, 0.7, 0.8, 0.9, 0.95):
+            r.found = torch.empty(N_FIND, dtype=torch.uint8, device=dev)
+            for load in loads:
                 n = int(load * (1 << LOG2_SLOTS))
-                nq_hit = synth.find_queries(W_KEY, KEY_SEED, n, N_FIND, 0.5, Q_SEED + 7, device=dev)
-                r.queries = nq_hit
-                r.found = torch.empty(N_FIND, dtype=torch.uint8, device=dev)
+                r.queries = qs[load]
                 for rep in range(3):
                     r.step(seed=77 + rep, n_ins=n, record=rep > 0)
                 ins, fnd = r.times_ms()
                 full = int((r.out[:n] == cpht.FULL).sum().item())
-                sweep.append({"slot_bits": slot_bits, "compact": bool(cmp_), "load": load,
+                sweep.append({"slot_bits": slot_bits, "compact": bool(cmp_), "bucket": bucket,
+                              "bucket_bytes": bucket * slot_bits // 8, "load": load,
                               "insert_mops": round(n / (sum(ins) / len(ins) / 1000.0) / 1e6, 1),
                               "find_mops": round(N_FIND / (sum(fnd) / len(fnd) / 1000.0) / 1e6, 1),
                               "full": full})
             del t, r
+        del qs
         res["sweep"] = sweep
 
     res["small_cuckoo"] = small_cuckoo(torch, cpht, synth, dev)
@@ -731,6 +867,9 @@ def main():
 
     if not args.no_iceberg:
         res["iceberg_zipf"] = iceberg_zipf(torch, cpht, synth, dev)
+
+    if not args.no_iceberg:
+        res["find_or_put"] = find_or_put(torch, cpht, synth, dev)
 
     if not args.no_many:
         res["many_tables"] = many_tables(torch, cpht, synth, dev)

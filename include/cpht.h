@@ -137,6 +137,29 @@ cpht_status_t cpht_find(cpht_table_t t, const void* d_keys, uint64_t n, uint8_t*
 cpht_status_t cpht_mixed(cpht_table_t t, const void* d_keys, const uint8_t* d_ops, uint64_t n, uint8_t* d_out,
                          void* stream);
 
+/* Cuckoo only: find-or-put by sorting the batch, the baseline of the paper's
+ * find-or-put experiment (Sec. 5, find-or-put benchmark): the keys are
+ * sorted with their positions to find duplicates, every distinct key is
+ * looked up once, and each distinct key that was absent is inserted once
+ * with the cuckoo put.  Keys may repeat and may already be stored.
+ * d_out[i] = CPHT_FOUND if keys[i] was in the table before the call, else
+ * the put's answer at the first occurrence of the key in the batch
+ * (CPHT_PUT, or CPHT_FULL when the eviction chain exceeded max_chain; the
+ * key dropped then is the carried one, as for cpht_insert) and CPHT_FOUND at
+ * its later occurrences (CPHT_FULL if the first got CPHT_FULL).  No other
+ * call may use the table concurrently.  n < 2^32.
+ * d_workspace: caller-owned device memory of at least
+ * cpht_sorted_fop_workspace(t, n) bytes, 256-byte aligned, used as scratch
+ * by the call (contents undefined afterwards; not to be shared by calls that
+ * overlap).  CPHT_E_STATE on an iceberg table (its insert is already a
+ * find-or-put), CPHT_E_ARG if the workspace is too small or misaligned. */
+cpht_status_t cpht_sorted_fop(cpht_table_t t, const void* d_keys, uint64_t n, uint8_t* d_out, void* d_workspace,
+                              uint64_t workspace_bytes, void* stream);
+
+/* Workspace bytes cpht_sorted_fop needs for n keys on table t (about 40
+ * bytes per key with 64-bit key words, 28 with 32-bit ones). */
+cpht_status_t cpht_sorted_fop_workspace(cpht_table_t t, uint64_t n, uint64_t* bytes);
+
 /* Occupied slots and total slots over all levels (fill factor = occupied /
  * capacity, Sec. 2.1).  Synchronises `stream`. */
 cpht_status_t cpht_count(cpht_table_t t, uint64_t* occupied, uint64_t* capacity, void* stream);

@@ -70,6 +70,8 @@ _SIGNATURES = {
     "cpht_bulk_build": (_I32, [_VP, _VP, _U64, _VP, _VP]),
     "cpht_find": (_I32, [_VP, _VP, _U64, _VP, _VP]),
     "cpht_mixed": (_I32, [_VP, _VP, _VP, _U64, _VP, _VP]),
+    "cpht_sorted_fop": (_I32, [_VP, _VP, _U64, _VP, _VP, _U64, _VP]),
+    "cpht_sorted_fop_workspace": (_I32, [_VP, _U64, ctypes.POINTER(_U64)]),
     "cpht_count": (_I32, [_VP, ctypes.POINTER(_U64), ctypes.POINTER(_U64), _VP]),
     "cpht_level_bytes": (_I32, [_VP, _U32, ctypes.POINTER(_U64)]),
     "cpht_level_ptr": (_I32, [_VP, _U32, ctypes.POINTER(_VP)]),
@@ -268,6 +270,28 @@ class Table:
         out = self._out(out, n, keys)
         _check(lib().cpht_mixed(self._h, self._keys(keys), _dev_ptr(ops, "ops"), n, _dev_ptr(out, "out"),
                                 _stream(stream)), "cpht_mixed")
+        return out
+
+    def sorted_fop_workspace(self, n: int) -> int:
+        b = _U64(0)
+        _check(lib().cpht_sorted_fop_workspace(self._h, n, ctypes.byref(b)), "cpht_sorted_fop_workspace")
+        return b.value
+
+    def sorted_fop(self, keys: torch.Tensor, out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+                   stream=None) -> torch.Tensor:
+        """Cuckoo find-or-put by sorting the batch (duplicates and stored keys
+        allowed).  `workspace`: a uint8 device tensor of at least
+        sorted_fop_workspace(n) bytes, allocated here when not given."""
+        n = keys.numel()
+        out = self._out(out, n, keys)
+        need = self.sorted_fop_workspace(n)
+        if workspace is None:
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=keys.device)
+        if workspace.dtype != torch.uint8 or workspace.numel() < need:
+            raise ValueError(f"workspace must be a uint8 device tensor of at least {need} bytes")
+        _check(lib().cpht_sorted_fop(self._h, self._keys(keys), n, _dev_ptr(out, "out"),
+                                     _dev_ptr(workspace, "workspace"), workspace.numel(), _stream(stream)),
+               "cpht_sorted_fop")
         return out
 
     def split(self, perm_index: int, keys: torch.Tensor, stream=None):

@@ -11,6 +11,7 @@
 #include "cpht_device.hpp"
 #include "cpht_registry.hpp"
 #include "cpht_roofline.hpp"
+#include "cpht_sortfop.hpp"
 #include "cpht_util.hpp"
 #include "cpht_internal.hpp"
 
@@ -320,6 +321,32 @@ cpht_status_t cpht_mixed(cpht_table_t t, const void* d_keys, const uint8_t* d_op
   if (!g.ok) return CPHT_E_DEVICE;
   t->ice->mixed(t->tk, batch(d_keys, d_ops, d_out, n), as_stream(stream));
   return launched();
+}
+
+cpht_status_t cpht_sorted_fop_workspace(cpht_table_t t, uint64_t n, uint64_t* bytes) {
+  if (!t || !bytes) return CPHT_E_ARG;
+  if (!t->ck) return CPHT_E_STATE;
+  if (n >= (1ull << 32)) return CPHT_E_ARG;
+  *bytes = sorted_fop_workspace(n, t->cfg.key_bits > 32 ? 8 : 4);
+  return CPHT_OK;
+}
+
+cpht_status_t cpht_sorted_fop(cpht_table_t t, const void* d_keys, uint64_t n, uint8_t* d_out, void* d_workspace,
+                              uint64_t workspace_bytes, void* stream) {
+  if (!t) return CPHT_E_ARG;
+  if (!t->ck) return CPHT_E_STATE;
+  if (n == 0) return CPHT_OK;
+  if (!d_keys || !d_out || !d_workspace || n >= (1ull << 32)) return CPHT_E_ARG;
+  if (reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0) return CPHT_E_ARG;
+  if (workspace_bytes < sorted_fop_workspace(n, t->cfg.key_bits > 32 ? 8 : 4)) return CPHT_E_ARG;
+  DeviceGuard g(t->device);
+  if (!g.ok) return CPHT_E_DEVICE;
+  int cus = 0;
+  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, t->device);
+  if (e != hipSuccess) return device_status(e);
+  e = launch_sorted_fop(t->tk, t->ck, (int)t->cfg.key_bits, d_keys, n, d_out, d_workspace,
+                        (uint32_t)(cus > 0 ? cus * 8 : 2048), as_stream(stream));
+  return device_status(e);
 }
 
 cpht_status_t cpht_count(cpht_table_t t, uint64_t* occupied, uint64_t* capacity, void* stream) {

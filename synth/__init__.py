@@ -134,6 +134,20 @@ def insert_stream_with_duplicates(w: int, key_seed: int, fresh_start: int, n_ops
     return feistel(w, key_seed, idx), n_fresh
 
 
+def find_or_put_batch(w: int, key_seed: int, n_before: int, n_new: int, n_ops: int, seed: int, device="cpu"):
+    """A find-or-put batch over a table holding phi(0 .. n_before-1): every
+    fresh key phi(n_before + j), j < n_new, occurs at least once, and the
+    other n_ops - n_new operations repeat keys drawn uniformly (with
+    replacement) from phi(0 .. n_before + n_new - 1), stored and fresh alike;
+    all in a seeded random order.  Returns (keys, idx) with keys = phi(idx)."""
+    if n_ops < n_new:
+        raise ValueError("n_ops must cover every fresh key")
+    fresh = torch.arange(n_before, n_before + n_new, dtype=torch.int64, device=device)
+    extra = uniform_below(seed, n_ops - n_new, max(1, n_before + n_new), device)
+    idx = torch.cat([fresh, extra])[permutation(seed + 1, n_ops, device)]
+    return feistel(w, key_seed, idx), idx
+
+
 def zipf_ranks(s: float, n: int, count: int, seed: int, device="cpu") -> torch.Tensor:
     """count i.i.d. draws from Zipf(s) on {1, ..., n} (P(k) proportional to
     k^-s, s > 0, s != 1), by rejection-inversion (W. Hormann and G. Derflinger,

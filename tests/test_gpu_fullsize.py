@@ -106,3 +106,54 @@ def test_c5_table_shape_full_size(gpu):
     assert puts == n and t.count() == (n, cap)
     q, truth = _queries(w, n, 1 << 24, 7, gpu)
     assert torch.equal(t.find(q), truth)
+
+
+def _fop_truth(idx, n_before, dev):
+    """Per-position answers of a find-or-put batch: FOUND for stored keys,
+    PUT at the first position of each fresh key, FOUND at its later ones."""
+    n_ops = idx.numel()
+    pos = torch.arange(n_ops, device=dev)
+    first = torch.full((int(idx.max().item()) + 1,), n_ops, dtype=torch.int64, device=dev)
+    first.scatter_reduce_(0, idx, pos, reduce="amin")
+    put = (idx >= n_before) & (first[idx] == pos)
+    return torch.where(put, cpht.PUT, cpht.FOUND).to(torch.uint8)
+
+
+def test_cuckoo_sorted_fop_full_size(gpu):
+    """The find-or-put experiment's cuckoo side at full size: 2^27 slots
+    filled to 0.5, then one sorted find-or-put of 2^27 keys (stored and fresh
+    keys, with repeats) that takes it to exactly 0.9.  Answers are unique
+    (the sort is stable), so they are compared per position."""
+    w, L = 37, 27
+    slots = 1 << L
+    n_before, n_after = slots // 2, int(0.9 * slots)
+    t = cpht.Table(scheme=cpht.CUCKOO, key_bits=w, log2_slots0=L, bucket0=32, slot_bits0=32, seed=81)
+    t.bulk_build(synth.distinct_keys(w, SEED, 0, n_before, device=gpu))
+    keys, idx = synth.find_or_put_batch(w, SEED, n_before, n_after - n_before, slots, 17, device=gpu)
+    out = t.sorted_fop(keys)
+    truth = _fop_truth(idx, n_before, gpu)
+    assert torch.equal(out, truth)
+    assert t.count() == (n_after, slots)
+    q, hit = _queries(w, n_after, 1 << 24, 8, gpu)
+    assert torch.equal(t.find(q), hit)
+
+
+def test_iceberg_fop_full_size(gpu):
+    """The iceberg side of the same experiment: 2^27 + 2^24 slots filled to
+    0.5, one find-or-put batch of 2^27 + 2^24 keys taking it to 0.9.  Which
+    repeat of a fresh key gets the PUT is timing-dependent, so the check is
+    per key: exactly one PUT for each fresh key, FOUND everywhere else."""
+    w, L0 = 37, 27
+    cap = (1 << L0) + (1 << (L0 - 3))
+    n_before, n_after = cap // 2, int(0.9 * cap)
+    t = cpht.Table(scheme=cpht.ICEBERG, key_bits=w, log2_slots0=L0, log2_slots1=L0 - 3, bucket0=32, bucket1=16,
+                   slot_bits0=16, slot_bits1=32, seed=82)
+    t.insert(synth.distinct_keys(w, SEED, 0, n_before, device=gpu))
+    keys, idx = synth.find_or_put_batch(w, SEED, n_before, n_after - n_before, cap, 18, device=gpu)
+    out = t.insert(keys)
+    assert not bool((out == cpht.FULL).any())
+    puts = torch.zeros(n_after, dtype=torch.int64, device=gpu)
+    puts.scatter_add_(0, idx, (out == cpht.PUT).to(torch.int64))
+    assert bool((puts[:n_before] == 0).all()) and bool((puts[n_before:] == 1).all())
+    assert bool(((out == cpht.PUT) | (out == cpht.FOUND)).all())
+    assert t.count() == (n_after, cap)

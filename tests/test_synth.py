@@ -95,3 +95,15 @@ def test_zipf_head_share_large_domain():
     N = float(1 << 34)
     norm = zeta(1.1) - N ** (-0.1) / 0.1 + 0.5 * N ** -1.1
     assert abs(share - 1.0 / norm) < 0.004, share
+
+
+def test_find_or_put_batch_structure():
+    keys, idx = synth.find_or_put_batch(30, 7, 1000, 500, 4000, 3)
+    assert keys.numel() == idx.numel() == 4000
+    assert int(idx.min()) >= 0 and int(idx.max()) < 1500
+    # every fresh index occurs, and the batch is a shuffle (fresh keys not all in front)
+    assert torch.isin(torch.arange(1000, 1500), idx).all()
+    assert not bool((idx[:500] >= 1000).all())
+    assert torch.equal(keys, synth.feistel(30, 7, idx))
+    k2, i2 = synth.find_or_put_batch(30, 7, 1000, 500, 4000, 3)
+    assert torch.equal(i2, idx)
