@@ -114,6 +114,11 @@ class Runner:
         return ins, fnd
 
 
+# Optional sections of the JSON line (each has a --no-<name> switch or is
+# picked with --only).
+SECTIONS = ("plain", "equal", "window", "sweep", "small", "iceberg", "fop", "delete", "many", "serving", "ceilings",
+            "cpu")
+
 # (slot bits, compact, slots per bucket) of the load sweep: compact 32-bit and
 # plain 64-bit slots at 8, 16 and 32 slots per bucket.
 SWEEP_SHAPES = ((32, 1, 32), (64, 0, 32), (32, 1, 16), (64, 0, 16), (32, 1, 8), (64, 0, 8))
@@ -226,6 +231,44 @@ def find_or_put(torch, cpht, synth, dev, reps=3):
     m = {r["before"]: r["mops"] for r in res["iceberg_16_32"]}
     c = {r["before"]: r["mops"] for r in res["cuckoo_32"]}
     res["iceberg_vs_sorted_cuckoo"] = {str(k): round(m[k] / c[k], 2) for k in m if k in c}
+    return res
+
+
+def deletes(torch, cpht, synth, dev, reps=3):
+    """Delete by tombstone on the compact cuckoo (2^27 slots) and compact
+    iceberg (2^27 + 2^24 slots, 16/32-bit) tables at load 0.9: one batch of
+    2^26 deletes, half of them stored keys and half absent keys; the table is
+    rebuilt (untimed) before each rep."""
+    w, L, nd = 37, 27, 1 << 26
+    res = {"config": "2^26 deletes (50% stored keys, 50% absent) on a table at load 0.9, 37-bit keys"}
+    for name, kw in (("cuckoo_32", dict(scheme=cpht.CUCKOO, key_bits=w, log2_slots0=L, bucket0=32, slot_bits0=32,
+                                        seed=9)),
+                     ("iceberg_16_32", dict(scheme=cpht.ICEBERG, key_bits=w, log2_slots0=L, log2_slots1=L - 3,
+                                            bucket0=32, bucket1=16, slot_bits0=16, slot_bits1=32, seed=9))):
+        t = cpht.Table(**kw)
+        cap = t.count()[1]
+        n = int(0.9 * cap)
+        keys = synth.distinct_keys(w, KEY_SEED + 5, 0, n, device=dev)
+        # the hits must be distinct for an exact check: draw them as a prefix of a permutation
+        hit_idx = synth.permutation(77, n, device=dev)[: nd // 2]
+        q = torch.cat([keys[hit_idx], synth.distinct_keys(w, KEY_SEED + 5, n, nd // 2, device=dev)])
+        q = q[synth.permutation(78, nd, device=dev)]
+        out = torch.empty(nd, dtype=torch.uint8, device=dev)
+        times, ok = [], True
+        for rep in range(reps + 1):
+            t.clear(90 + rep)
+            t.insert(keys)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            t.delete(q, out)
+            b.record()
+            b.synchronize()
+            ok = ok and int(out.sum().item()) == nd // 2 and t.count()[0] == n - nd // 2
+            if rep:
+                times.append(a.elapsed_time(b))
+        ms = sum(times) / len(times)
+        res[name] = {"ms": round(ms, 3), "mops": round(nd / (ms / 1000.0) / 1e6, 1), "check": "ok" if ok else "FAILED"}
+        del t, keys, q, out
     return res
 
 
@@ -688,9 +731,23 @@ def main():
     ap.add_argument("--no-iceberg", action="store_true", help="skip the iceberg sections")
     ap.add_argument("--no-many", action="store_true", help="skip the many-table section")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop section")
+    ap.add_argument("--only", default="",
+                    help="comma list of extra sections to run beside the headline step, all others skipped: "
+                         + ",".join(SECTIONS))
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (reference kernel for HBM byte counters)")
     args = ap.parse_args()
+    if args.only:
+        want = set(args.only.split(","))
+        unknown = want - set(SECTIONS)
+        if unknown:
+            ap.error(f"unknown sections {sorted(unknown)}")
+        for sec in SECTIONS:
+            setattr(args, "no_" + sec, sec not in want)
+    else:
+        for sec in SECTIONS:
+            if not hasattr(args, "no_" + sec):
+                setattr(args, "no_" + sec, False)
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path has no multi-GPU "
@@ -826,10 +883,11 @@ def main():
         }
         del plain, prun
 
-    if not args.no_plain:
+    if not args.no_plain and not args.no_equal:
         res["equal_memory"] = equal_memory(torch, cpht, keys, queries, n_ins)
 
-    res["marginal_window"] = marginal_window(torch, cpht, keys, n_ins)
+    if not args.no_window:
+        res["marginal_window"] = marginal_window(torch, cpht, keys, n_ins)
 
     if not args.no_sweep:
         loads = (0.5, 0.7, 0.8, 0.9, 0.95)
@@ -859,17 +917,19 @@ def main():
         del qs
         res["sweep"] = sweep
 
-    res["small_cuckoo"] = small_cuckoo(torch, cpht, synth, dev)
+    if not args.no_small:
+        res["small_cuckoo"] = small_cuckoo(torch, cpht, synth, dev)
 
     if not args.no_iceberg:
         res["iceberg_static"] = iceberg_static(torch, cpht, synth, dev)
         res["iceberg_mixed"] = iceberg_mixed(torch, cpht, synth, dev)
-
-    if not args.no_iceberg:
         res["iceberg_zipf"] = iceberg_zipf(torch, cpht, synth, dev)
 
-    if not args.no_iceberg:
+    if not args.no_fop:
         res["find_or_put"] = find_or_put(torch, cpht, synth, dev)
+
+    if not args.no_delete:
+        res["delete"] = deletes(torch, cpht, synth, dev)
 
     if not args.no_many:
         res["many_tables"] = many_tables(torch, cpht, synth, dev)

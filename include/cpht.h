@@ -130,6 +130,20 @@ cpht_status_t cpht_bulk_build(cpht_table_t t, const void* d_keys, uint64_t n, ui
  * both secondary buckets only when the primary is full (Sec. 2.3 "Lookup"). */
 cpht_status_t cpht_find(cpht_table_t t, const void* d_keys, uint64_t n, uint8_t* d_found, void* stream);
 
+/* Delete a batch by tombstones (Sec. 2.2 "Lookup" and Sec. 3 "Limitations"):
+ * the slot holding keys[i] gets the tombstone word 1, which is not EMPTY and
+ * matches no key, so non-empty slots stay consecutive and lookups keep their
+ * early exit.  d_out[i] = 1 if this call removed keys[i], else 0 (absent, or
+ * removed by another delete of the same key in the batch: exactly one
+ * operation per stored key answers 1).  Tombstones are not reclaimed by
+ * find-or-put or by the first-empty claim of the cuckoo put (a cuckoo
+ * eviction that picks one as its victim overwrites it); they are counted by
+ * neither cpht_count nor the fill factor, but keep their slots until
+ * cpht_clear.  Iceberg: may run concurrently with cpht_find and other
+ * deletes (a find of a key being deleted may answer either way).  Cuckoo: no
+ * put may run concurrently. */
+cpht_status_t cpht_delete(cpht_table_t t, const void* d_keys, uint64_t n, uint8_t* d_out, void* stream);
+
 /* Iceberg only: one batch of finds (d_ops[i] = CPHT_OP_FIND, answer 0/1) and
  * find-or-puts (CPHT_OP_INSERT, answer PUT/FOUND/FULL) executed concurrently
  * (dynamic operation, Sec. 1 and Sec. 3).  A find of a key that another
@@ -160,8 +174,8 @@ cpht_status_t cpht_sorted_fop(cpht_table_t t, const void* d_keys, uint64_t n, ui
  * bytes per key with 64-bit key words, 28 with 32-bit ones). */
 cpht_status_t cpht_sorted_fop_workspace(cpht_table_t t, uint64_t n, uint64_t* bytes);
 
-/* Occupied slots and total slots over all levels (fill factor = occupied /
- * capacity, Sec. 2.1).  Synchronises `stream`. */
+/* Slots holding a key (tombstones excluded) and total slots over all levels
+ * (fill factor = occupied / capacity, Sec. 2.1).  Synchronises `stream`. */
 cpht_status_t cpht_count(cpht_table_t t, uint64_t* occupied, uint64_t* capacity, void* stream);
 
 /* Size in bytes of level `level` (0, or 1 for the iceberg secondary level). */

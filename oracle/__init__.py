@@ -101,6 +101,10 @@ def lib():
         L.or_mixed.argtypes = [vp, vp, vp, u64, vp]
         L.or_occupied.restype = u64
         L.or_occupied.argtypes = [vp]
+        L.or_tombstones.restype = u64
+        L.or_tombstones.argtypes = [vp]
+        L.or_delete.restype = i32
+        L.or_delete.argtypes = [vp, vp, u64, vp]
         L.or_capacity.restype = u64
         L.or_capacity.argtypes = [vp]
         L.or_level_bytes.restype = u64
@@ -235,8 +239,18 @@ class Table:
             raise ValueError("mixed batches need an iceberg table")
         return out
 
+    def delete(self, keys):
+        """Delete by tombstone, in order: 1 where the key was stored, else 0."""
+        k = _u64(keys)
+        out = np.zeros(k.size, np.uint8)
+        lib().or_delete(self._h, _ptr(k), k.size, _ptr(out))
+        return out
+
     def occupied(self) -> int:
         return int(lib().or_occupied(self._h))
+
+    def tombstones(self) -> int:
+        return int(lib().or_tombstones(self._h))
 
     def capacity(self) -> int:
         return int(lib().or_capacity(self._h))

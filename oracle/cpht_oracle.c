@@ -21,11 +21,15 @@
  *   3. Slot encoding: EMPTY is the all-zero word; an occupied slot holds an
  *      occupancy bit, a tag (hash index j for cuckoo, Sec. 2.2 / Alg. 4; the
  *      secondary index for iceberg, Sec. 3 Alg. 1) and the remainder
- *      (Sec. 2.4), or the full permuted key for a non-compact table.
+ *      (Sec. 2.4), or the full permuted key for a non-compact table.  A
+ *      deleted key leaves a tombstone, the word 1 (occupancy bit clear): a
+ *      slot that is not EMPTY but holds no key, so non-empty slots stay
+ *      consecutive (Sec. 2.2 "Lookup", Sec. 3 "Limitations").
  *   4. Iceberg find-or-put, run sequentially as the simplified find-or-put of
  *      Appendix A (Alg. 5) over the slot order of Definition 1.
  *   5. Iceberg lookup (Sec. 2.3 "Lookup", levels 1 and 2).
  *   6. Compact cuckoo put (Sec. 4.4, Alg. 4) and lookup (Sec. 4.4 "Lookup").
+ *   6b. Delete by tombstone, both schemes.
  *   7. A table checker for raw table images (well-formedness and the order
  *      property of Appendix A Definition 2, no duplicates (Lemma 1), prefix
  *      filling, and the cuckoo early-exit invariant of Sec. 2.2 / 4.4).
@@ -154,6 +158,7 @@ int or_perm_constants(uint32_t w, uint64_t seed, uint32_t i, uint64_t* m3, uint6
 
 enum { OR_CUCKOO = 0, OR_ICEBERG = 1 };
 enum { OR_NONE = 0, OR_PUT = 1, OR_FOUND = 2, OR_FULL = 3 };
+#define OR_TOMB 1ULL /* tombstone: not EMPTY, occupancy bit clear, matches no stored form */
 
 /* Field order mirrors the ctypes structure in oracle/__init__.py. */
 typedef struct {
@@ -290,6 +295,10 @@ static uint64_t dec_of(const or_table_t* t, const or_level_t* L, uint32_t i, uin
 static uint64_t tag_of(const or_level_t* L, uint64_t v) { return (v >> L->pbits) & wmask(L->tbits); }
 
 static uint64_t* bucket_ptr(or_level_t* L, uint64_t b) { return L->slot + b * L->B; }
+
+/* A slot value holds a key iff its occupancy bit is set (EMPTY and the
+ * tombstone both have it clear). */
+static int holds_key(const or_level_t* L, uint64_t v) { return (int)((v >> (L->s - 1)) & 1); }
 
 /* Cache lines touched by reading one whole bucket. */
 static uint32_t bucket_lines(const or_table_t* t, const or_level_t* L)
@@ -455,6 +464,7 @@ static int ck_put_one(or_table_t* t, uint64_t k, uint32_t* lines)
         uint32_t i = ck_victim(k, c, L->B);
         uint64_t old = b[i];
         b[i] = v;
+        if (!holds_key(L, old)) return OR_PUT; /* the victim was a tombstone: nothing to carry */
         uint32_t jj = (uint32_t)tag_of(L, old);
         k = dec_of(t, L, jj, a, old);
         j = (jj + 1) % H;
@@ -480,6 +490,41 @@ static int ck_find_one(or_table_t* t, uint64_t k, uint32_t* lines)
             if (b[i] == 0) has_empty = 1;
         }
         if (has_empty) return 0;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 6b. Delete by tombstone                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Delete k: the slot holding k's stored form (in any of the buckets k may
+ * occupy: a_0..a_{H-1} for cuckoo; primary and both secondaries for iceberg)
+ * becomes a tombstone.  A key is stored at most once, so the first match is
+ * the only one.  Returns 1 if k was stored, else 0.  Tombstones are never
+ * written back to EMPTY: lookups and the prefix rule treat them as occupied,
+ * find-or-put and the first-empty claim never reuse them, and a cuckoo
+ * eviction that picks one as its victim simply overwrites it. */
+static int del_one(or_table_t* t, uint64_t k)
+{
+    if (t->cfg.scheme == OR_ICEBERG) {
+        or_ice_key_t q;
+        ice_key(t, k, &q);
+        for (uint32_t x = 0; x <= 2; ++x) {
+            uint32_t By = x == 0 ? t->cfg.B0 : t->cfg.B1;
+            for (uint32_t y = 0; y < By; ++y) {
+                uint64_t* s = ice_slot(t, &q, x, y);
+                if (*s == q.e[x]) { *s = OR_TOMB; return 1; }
+            }
+        }
+        return 0;
+    }
+    or_level_t* L = &t->lv[0];
+    for (uint32_t j = 0; j < t->cfg.H; ++j) {
+        uint64_t* b = bucket_ptr(L, addr_of(t, L, j, k));
+        uint64_t v = enc_of(t, L, j, k, j);
+        for (uint32_t i = 0; i < L->B; ++i)
+            if (b[i] == v) { b[i] = OR_TOMB; return 1; }
     }
     return 0;
 }
@@ -516,6 +561,12 @@ int or_find(or_table_t* t, const uint64_t* keys, uint64_t n, uint8_t* out, uint3
     return 0;
 }
 
+int or_delete(or_table_t* t, const uint64_t* keys, uint64_t n, uint8_t* out)
+{
+    for (uint64_t i = 0; i < n; ++i) out[i] = (uint8_t)del_one(t, keys[i]);
+    return 0;
+}
+
 /* Mixed batch: op 0 = find (answer 0/1), op 1 = insert (PUT/FOUND/FULL),
  * applied in index order.  Iceberg only: cuckoo is static (Sec. 4.4). */
 int or_mixed(or_table_t* t, const uint64_t* keys, const uint8_t* ops, uint64_t n, uint8_t* out)
@@ -533,12 +584,22 @@ int or_mixed(or_table_t* t, const uint64_t* keys, const uint8_t* ops, uint64_t n
     return 0;
 }
 
-/* Occupied slots over all levels (the numerator of the fill factor, Sec. 2.1). */
+/* Slots holding a key over all levels (the numerator of the fill factor,
+ * Sec. 2.1; tombstones hold no key). */
 uint64_t or_occupied(const or_table_t* t)
 {
     uint64_t c = 0;
     for (int x = 0; x < t->nlevels; ++x)
-        for (uint64_t i = 0; i < t->lv[x].nslots; ++i) c += t->lv[x].slot[i] != 0;
+        for (uint64_t i = 0; i < t->lv[x].nslots; ++i) c += (uint64_t)holds_key(&t->lv[x], t->lv[x].slot[i]);
+    return c;
+}
+
+/* Tombstones over all levels. */
+uint64_t or_tombstones(const or_table_t* t)
+{
+    uint64_t c = 0;
+    for (int x = 0; x < t->nlevels; ++x)
+        for (uint64_t i = 0; i < t->lv[x].nslots; ++i) c += t->lv[x].slot[i] == OR_TOMB;
     return c;
 }
 
@@ -596,8 +657,9 @@ static int cmp_u64(const void* a, const void* b)
 
 /* Check raw level images against the configuration and return the decoded
  * key set (sorted) in keys_out (capacity >= occupied slots).  Checks:
- *   - every slot is EMPTY or a valid stored form: occupancy bit set, unused
- *     high bits clear, tag in range (Definition 2, first item);
+ *   - every slot is EMPTY, a tombstone, or a valid stored form: occupancy
+ *     bit set, unused high bits clear, tag in range (Definition 2, first
+ *     item);
  *   - the non-empty slots of every bucket form a prefix (inserts always take
  *     the first empty slot, Alg. 1/2/4; the cuckoo lookup relies on it);
  *   - for a non-compact table the stored pi_j(k) addresses its own bucket;
@@ -628,6 +690,7 @@ int or_check(const or_cfg_t* c, const void* img0, const void* img1, uint64_t* ke
                 uint64_t v = bk[y];
                 if (v == 0) { seen_empty = 1; continue; }
                 if (seen_empty) FAIL("level %d bucket %llu: slot %u filled after an empty slot", x, (unsigned long long)b, y);
+                if (v == OR_TOMB) continue;
                 if (!(v >> (L->s - 1) & 1)) FAIL("level %d bucket %llu slot %u: occupancy bit clear", x, (unsigned long long)b, y);
                 if (used < (uint64_t)L->s - 1 && (v & ~(1ULL << (L->s - 1))) >> used)
                     FAIL("level %d bucket %llu slot %u: stray high bits", x, (unsigned long long)b, y);

@@ -41,6 +41,19 @@ def insert(S: np.ndarray, keys):
     return out, np.union1d(S, k)
 
 
+def delete(S: np.ndarray, keys):
+    """Deletions applied in index order to S.
+
+    Returns (answers, S_after): 1 at the first occurrence of every key of S
+    (that operation removes it), 0 for keys not in S and for repeats."""
+    k = np.asarray(keys, dtype=np.uint64)
+    out = np.zeros(k.size, np.uint8)
+    _, first = np.unique(k, return_index=True)
+    hit = first[np.isin(k[first], S)]
+    out[hit] = 1
+    return out, np.setdiff1d(S, k)
+
+
 def mixed(S: np.ndarray, keys, ops):
     """Finds (op 0) and inserts (op 1) applied in index order to S.
 

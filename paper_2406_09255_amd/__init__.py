@@ -70,6 +70,7 @@ _SIGNATURES = {
     "cpht_bulk_build": (_I32, [_VP, _VP, _U64, _VP, _VP]),
     "cpht_find": (_I32, [_VP, _VP, _U64, _VP, _VP]),
     "cpht_mixed": (_I32, [_VP, _VP, _VP, _U64, _VP, _VP]),
+    "cpht_delete": (_I32, [_VP, _VP, _U64, _VP, _VP]),
     "cpht_sorted_fop": (_I32, [_VP, _VP, _U64, _VP, _VP, _U64, _VP]),
     "cpht_sorted_fop_workspace": (_I32, [_VP, _U64, ctypes.POINTER(_U64)]),
     "cpht_count": (_I32, [_VP, ctypes.POINTER(_U64), ctypes.POINTER(_U64), _VP]),
@@ -270,6 +271,14 @@ class Table:
         out = self._out(out, n, keys)
         _check(lib().cpht_mixed(self._h, self._keys(keys), _dev_ptr(ops, "ops"), n, _dev_ptr(out, "out"),
                                 _stream(stream)), "cpht_mixed")
+        return out
+
+    def delete(self, keys: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Delete by tombstone: out[i] = 1 if this call removed keys[i]."""
+        n = keys.numel()
+        out = self._out(out, n, keys)
+        _check(lib().cpht_delete(self._h, self._keys(keys), n, _dev_ptr(out, "out"), _stream(stream)),
+               "cpht_delete")
         return out
 
     def sorted_fop_workspace(self, n: int) -> int:

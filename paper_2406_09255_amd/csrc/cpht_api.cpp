@@ -311,6 +311,18 @@ cpht_status_t cpht_find(cpht_table_t t, const void* d_keys, uint64_t n, uint8_t*
   return launched();
 }
 
+cpht_status_t cpht_delete(cpht_table_t t, const void* d_keys, uint64_t n, uint8_t* d_out, void* stream) {
+  if (!t) return CPHT_E_ARG;
+  if (n == 0) return CPHT_OK;
+  if (!d_keys || !d_out) return CPHT_E_ARG;
+  DeviceGuard g(t->device);
+  if (!g.ok) return CPHT_E_DEVICE;
+  const BatchK b = batch(d_keys, nullptr, d_out, n);
+  if (t->ice) t->ice->erase(t->tk, b, as_stream(stream));
+  else t->ck->erase(t->tk, b, as_stream(stream));
+  return launched();
+}
+
 cpht_status_t cpht_mixed(cpht_table_t t, const void* d_keys, const uint8_t* d_ops, uint64_t n, uint8_t* d_out,
                          void* stream) {
   if (!t) return CPHT_E_ARG;

@@ -33,19 +33,26 @@ struct Depth {
   static_assert(G % D == 0, "prefetch depth must divide the sub-tile");
 };
 
-// Batch kernel.  PUT = false: lookup; PUT = true: Alg. 4.
-//   lookup: buckets a_0(k), a_1(k), ... in order; a hit answers 1, a bucket
+enum : int { CK_FIND = 0, CK_PUT = 1, CK_ERASE = 2 };
+
+// Batch kernel, one operation per key:
+//   CK_FIND: buckets a_0(k), a_1(k), ... in order; a hit answers 1, a bucket
 //     that is not full and lacks (r_j(k), j) answers 0 (keys are only pushed
-//     to hash j+1 out of a full bucket, so k cannot be further on).
-//   put: per round, the bucket T[a_j(k)] of the carried key k is snapshotted;
-//     with an empty slot, the first one is claimed with CAS (a lost claim
-//     uses up the round and marks the slot known-occupied, so a stale re-read
-//     cannot offer it again); with no empty slot, the victim row chosen from
-//     (k, round) is swapped with (r_j(k), j) and the evicted pair (r', j')
-//     continues as key pi_{j'}^{-1}(a . r') with hash index j'+1 mod H.
-//     After C rounds the carried key is dropped and the result is FULL.
-template <class KeyT, int S, int B, int G, bool PUT>
+//     to hash j+1 out of a full bucket, so k cannot be further on; tombstones
+//     count as occupied, so deletes keep this true).
+//   CK_PUT: Alg. 4.  Per round, the bucket T[a_j(k)] of the carried key k is
+//     snapshotted; with an empty slot, the first one is claimed with CAS (a
+//     lost claim uses up the round and marks the slot known-occupied, so a
+//     stale re-read cannot offer it again); with no empty slot, the victim row
+//     chosen from (k, round) is swapped with (r_j(k), j) and the evicted pair
+//     (r', j') continues as key pi_{j'}^{-1}(a . r') with hash index j'+1 mod
+//     H; a tombstone as victim ends the chain (nothing is carried).  After C
+//     rounds the carried key is dropped and the result is FULL.
+//   CK_ERASE: the lookup's probe sequence; the slot holding (r_j(k), j) is
+//     replaced by the tombstone with CAS; answers 1 if this operation did it.
+template <class KeyT, int S, int B, int G, int OP>
 __device__ __forceinline__ void cuckoo_body(const TableK& T, const BatchK& Bt, uint64_t idx) {
+  constexpr bool PUT = OP == CK_PUT;
   using U = KeyT;
   using Sh = CkShape<S, B, G>;
   using KM = KnownMask<B>;
@@ -63,7 +70,7 @@ __device__ __forceinline__ void cuckoo_body(const TableK& T, const BatchK& Bt, u
 
 #pragma unroll 1
   while (__ballot(pend) != 0ull) {
-    bool claim = false, evict = false;
+    bool claim = false, evict = false, erase = false;
     uint32_t q = 0;
 #pragma unroll 1
     for (int t0 = 0; t0 < G; t0 += D) {
@@ -84,10 +91,18 @@ __device__ __forceinline__ void cuckoo_body(const TableK& T, const BatchK& Bt, u
         if (!live[d]) continue;
         const bool mine = st.rk == t0 + d;
         if constexpr (!PUT) {
-          const bool hit = st.ballot(lane_has<S, W>(buf[d], ev[d])) != 0u;
+          const uint32_t hits = st.ballot(lane_has<S, W>(buf[d], ev[d]));
           const bool room = st.ballot(lane_first_empty<S, W>(buf[d], 0u) < PER) != 0u;
-          if (mine && (hit || room)) {
-            result = hit ? 1 : 0;
+          if constexpr (OP == CK_ERASE) {
+            if (hits) {
+              const int f = ctz32(hits);
+              const uint32_t qq = (uint32_t)(f * PER) + st.bcast((uint32_t)lane_match<S, W>(buf[d], ev[d]), f);
+              if (mine) { erase = true; q = qq; pend = false; }
+              continue;
+            }
+          }
+          if (mine && (hits || room)) {
+            result = hits ? 1 : 0;
             pend = false;
           }
         } else {
@@ -104,6 +119,9 @@ __device__ __forceinline__ void cuckoo_body(const TableK& T, const BatchK& Bt, u
       }
     }
     if constexpr (!PUT) {
+      if constexpr (OP == CK_ERASE) {
+        if (erase) result = erase_at<S>(L.base + s.a * L.bucket_words, q, 0u, s.e) ? 1 : 0;
+      }
       if (pend) {  // the bucket was full without k: next hash function
         if (++j == T.H) { result = 0; pend = false; }
         else s = split_key<U, S>(T, L, (int)j, k, j);
@@ -120,11 +138,16 @@ __device__ __forceinline__ void cuckoo_body(const TableK& T, const BatchK& Bt, u
       } else if (evict) {
         const uint32_t v = victim_row((uint64_t)k, c, (uint32_t)B);
         const uint64_t old = swap_at<S>(bucket, v, s.e);
-        const uint32_t jj = (uint32_t)((old >> L.pbits) & ((1ull << L.tbits) - 1ull));
-        k = join_key<U>(T, L, (int)jj, s.a, old);
-        j = jj + 1 == T.H ? 0u : jj + 1;
-        s = split_key<U, S>(T, L, (int)j, k, j);
-        known = 0;
+        if (((old >> (S - 1)) & 1ull) == 0ull) {  // a tombstone: the chain ends here
+          result = R_PUT;
+          pend = false;
+        } else {
+          const uint32_t jj = (uint32_t)((old >> L.pbits) & ((1ull << L.tbits) - 1ull));
+          k = join_key<U>(T, L, (int)jj, s.a, old);
+          j = jj + 1 == T.H ? 0u : jj + 1;
+          s = split_key<U, S>(T, L, (int)j, k, j);
+          known = 0;
+        }
       }
       if (pend && ++c > T.C) {
         result = R_FULL;
@@ -136,13 +159,13 @@ __device__ __forceinline__ void cuckoo_body(const TableK& T, const BatchK& Bt, u
 }
 
 // One table: key i of the batch is handled by global thread i.
-template <class KeyT, int S, int B, int G, bool PUT>
+template <class KeyT, int S, int B, int G, int OP>
 __global__ __launch_bounds__(256) void cuckoo_kernel(TableK T, BatchK Bt) {
-  cuckoo_body<KeyT, S, B, G, PUT>(T, Bt, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  cuckoo_body<KeyT, S, B, G, OP>(T, Bt, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // Many tables in one persistent launch (see iceberg_multi_kernel).
-template <class KeyT, int S, int B, int G, bool PUT>
+template <class KeyT, int S, int B, int G, int OP>
 __global__ __launch_bounds__(256) void cuckoo_multi_kernel(MultiK M) {
   const uint64_t first = M.group[0], count = M.group[1];
 #pragma unroll 1
@@ -154,7 +177,7 @@ __global__ __launch_bounds__(256) void cuckoo_multi_kernel(MultiK M) {
     Bt.ops = nullptr;
     Bt.out = M.out + ch.start;
     Bt.n = ch.count;
-    cuckoo_body<KeyT, S, B, G, PUT>(T, Bt, threadIdx.x);
+    cuckoo_body<KeyT, S, B, G, OP>(T, Bt, threadIdx.x);
   }
 }
 

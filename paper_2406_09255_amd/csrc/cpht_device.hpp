@@ -70,6 +70,12 @@ struct MultiK {
 
 enum : uint8_t { R_NONE = 0, R_PUT = 1, R_FOUND = 2, R_FULL = 3 };
 
+// A deleted key leaves a tombstone: the word 1 in a slot of any width.  It is
+// not EMPTY (so the non-empty slots of a bucket stay consecutive and lookups
+// keep their early exit, Sec. 2.2 "Lookup", Sec. 3 "Limitations"), and with
+// its occupancy bit clear it equals no stored form.
+constexpr uint64_t TOMB = 1;
+
 // ---------------------------------------------------------------------------
 // Permutation pi_i on w-bit keys and its inverse.  U is uint32_t for w <= 32
 // and uint64_t otherwise; all arithmetic is modulo 2^w.
@@ -170,6 +176,16 @@ __device__ __forceinline__ bool lane_has(const uint32_t (&w)[W], uint64_t e) {
   return hit;
 }
 
+// Index of the slot held by this lane that equals e, or PER if there is none.
+template <int S, int W>
+__device__ __forceinline__ int lane_match(const uint32_t (&w)[W], uint64_t e) {
+  int f = Lane<S, W>::PER;
+#pragma unroll
+  for (int i = Lane<S, W>::PER - 1; i >= 0; --i)
+    if (slot_at<S, W>(w, i) == e) f = i;
+  return f;
+}
+
 // Index of the first slot held by this lane that is EMPTY in the snapshot
 // and not known to be occupied (bit i of `known`), or PER if there is none.
 template <int S, int W>
@@ -209,18 +225,6 @@ __device__ __forceinline__ void load_words(uint32_t (&w)[W], const uint32_t* p) 
   }
 }
 
-// Merge a fresh read into the snapshot.  Slots never go back to EMPTY
-// (iceberg slots are written once; a cuckoo swap replaces an occupied slot by
-// another occupied one), so a slot the snapshot knows to be occupied is still
-// occupied even if the fresh read is stale.  For iceberg an occupied slot
-// never changes, so OR reproduces the exact value; cuckoo insertion only uses
-// the snapshot to tell EMPTY from occupied, which OR also preserves.
-template <int W>
-__device__ __forceinline__ void merge_words(uint32_t (&w)[W], const uint32_t (&f)[W]) {
-#pragma unroll
-  for (int i = 0; i < W; ++i) w[i] |= f[i];
-}
-
 // ---------------------------------------------------------------------------
 // Atomics (agent scope: visible across all XCDs of the device)
 // ---------------------------------------------------------------------------
@@ -247,45 +251,16 @@ __device__ __forceinline__ uint64_t xchg64(uint64_t* p, uint64_t v) {
 
 enum : int { CLAIM_LOST = 0, CLAIM_WON = 1, CLAIM_SAME = 2 };
 
-// Claim lane-local slot i (EMPTY in the snapshot) for value e with a CAS.
-// Returns CLAIM_WON if this call stored e, CLAIM_SAME if the slot already
-// holds e (another thread stored the same key: the CAS result stands in for a
-// re-read, Sec. 4.2 implementation notes), CLAIM_LOST otherwise; in the last
-// two cases bit i of `known` records that the slot is occupied, so a stale
-// re-read cannot make it look EMPTY again.  16-bit slots have no native CAS:
-// the containing 32-bit word is compare-and-swapped, and the attempt repeats
-// only while the other half of the word is what changed (which happens at
-// most once, as a slot goes from EMPTY to occupied only once).
-template <int S, int W>
-__device__ __forceinline__ int claim_slot(uint32_t* lane_ptr, const uint32_t (&w)[W], uint32_t& known,
-                                          int i, uint64_t e) {
-  uint64_t got;
-  if constexpr (S == 32) {
-    got = cas32(lane_ptr + i, 0u, (uint32_t)e);
-  } else if constexpr (S == 64) {
-    got = cas64(reinterpret_cast<uint64_t*>(lane_ptr + 2 * i), 0ull, e);
-  } else {
-    const int wi = i >> 1;
-    const int sh = (i & 1) * 16;
-    const uint32_t mine = (uint32_t)e << sh;
-    uint32_t cur = get_word<W>(w, wi) & ~(0xFFFFu << sh);
-    for (;;) {
-      const uint32_t old = cas32(lane_ptr + wi, cur, cur | mine);
-      if (old == cur) { got = 0; break; }
-      got = (old >> sh) & 0xFFFFu;
-      if (got) break;
-      cur = old;
-    }
-  }
-  if (got == 0) return CLAIM_WON;
-  known |= 1u << i;
-  return got == e ? CLAIM_SAME : CLAIM_LOST;
-}
-
 // Claim slot q of the bucket starting at `bucket` for value e, by a single
 // lane on behalf of its own key (the pipelined paths let every key's owner
 // lane claim at once).  `word` is the snapshot of the 32-bit word holding the
-// slot (used by 16-bit slots only).  Same results as claim_slot.
+// slot (used by 16-bit slots only).  Returns CLAIM_WON if this call stored e,
+// CLAIM_SAME if the slot already holds e (another operation stored the same
+// key: the CAS result stands in for a re-read, Sec. 4.2 implementation
+// notes), CLAIM_LOST otherwise.  16-bit slots have no native CAS: the
+// containing 32-bit word is compare-and-swapped, and the attempt repeats only
+// while the other half of the word is what changed (a bounded number of
+// times: a slot goes from EMPTY to a key, and at most on to a tombstone).
 template <int S>
 __device__ __forceinline__ int claim_at(uint32_t* bucket, uint32_t q, uint32_t word, uint64_t e) {
   uint64_t got;
@@ -308,6 +283,30 @@ __device__ __forceinline__ int claim_at(uint32_t* bucket, uint32_t q, uint32_t w
   }
   if (got == 0) return CLAIM_WON;
   return got == e ? CLAIM_SAME : CLAIM_LOST;
+}
+
+// Delete: replace the stored form e in slot q by the tombstone.  True if
+// this call did it, false if the slot no longer holds e (a concurrent delete
+// of the same key won).  16-bit slots compare-and-swap the containing word,
+// repeating only while the other half of the word is what changed.
+template <int S>
+__device__ __forceinline__ bool erase_at(uint32_t* bucket, uint32_t q, uint32_t word, uint64_t e) {
+  if constexpr (S == 32) {
+    return cas32(bucket + q, (uint32_t)e, (uint32_t)TOMB) == (uint32_t)e;
+  } else if constexpr (S == 64) {
+    return cas64(reinterpret_cast<uint64_t*>(bucket + 2 * q), e, TOMB) == e;
+  } else {
+    const uint32_t wi = q >> 1;
+    const int sh = (int)(q & 1u) * 16;
+    const uint32_t keep = ~(0xFFFFu << sh);
+    uint32_t cur = (word & keep) | ((uint32_t)e << sh);
+    for (;;) {
+      const uint32_t old = cas32(bucket + wi, cur, (cur & keep) | ((uint32_t)TOMB << sh));
+      if (old == cur) return true;
+      if (((old >> sh) & 0xFFFFu) != (uint32_t)e) return false;
+      cur = old;
+    }
+  }
 }
 
 // Swap bucket slot q with value e (cuckoo eviction); returns the old value.

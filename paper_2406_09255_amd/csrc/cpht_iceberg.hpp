@@ -22,7 +22,7 @@
 
 namespace cpht {
 
-enum : int { MODE_FIND = 0, MODE_INSERT = 1, MODE_MIXED = 2 };
+enum : int { MODE_FIND = 0, MODE_INSERT = 1, MODE_MIXED = 2, MODE_ERASE = 3 };
 
 template <int S0, int S1, int B0, int B1, int G>
 struct IceShape {
@@ -55,8 +55,13 @@ struct IceDepth {
 //     Appendix A, Def. 1); FULL if the target bucket has no empty slot.
 //   A claim that finds k's own stored form in the slot answers FOUND.
 // MODE_MIXED reads a per-key opcode (0 = find, 1 = find-or-put).
+// MODE_ERASE follows the lookup and replaces the slot holding k's stored form
+// by the tombstone with CAS (answer 1 if this operation did it, else 0).
+// Tombstones count as occupied everywhere and are never claimed, so the
+// order property and the lookup's early exit hold with deletes.
 template <class KeyT, int S0, int S1, int B0, int B1, int G, int MODE>
 __device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, uint64_t idx) {
+  constexpr bool WRITES = MODE == MODE_INSERT || MODE == MODE_MIXED;  // find-or-put claims
   using U = KeyT;
   using Sh = IceShape<S0, S1, B0, B1, G>;
   using KM0 = KnownMask<B0>;
@@ -85,7 +90,7 @@ __device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, 
   while (__ballot(stage != 0u) != 0ull) {
     // ------------------------------------------------------------ level 1
     if (__ballot(stage == 1u) != 0ull) {
-      bool claim = false;
+      bool claim = false, erase = false;
       uint32_t q = 0, word = 0;
 #pragma unroll 1
       for (int t0 = 0; t0 < G; t0 += D0) {
@@ -98,7 +103,7 @@ __device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, 
           live[d] = st.bcast(stage, t0 + d) == 1u;
           const uint32_t a = st.bcast((uint32_t)s0.a, t0 + d);
           ev[d] = st.template bcast_slot<S0>(s0.e, t0 + d);
-          if constexpr (MODE != MODE_FIND) kn[d] = st.bcast_mask(known0, t0 + d);
+          if constexpr (WRITES) kn[d] = st.bcast_mask(known0, t0 + d);
           if (live[d]) load_words<W0>(buf[d], L0.base + (uint64_t)a * L0.bucket_words + (uint32_t)(st.rk * W0));
         }
 #pragma unroll
@@ -106,12 +111,21 @@ __device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, 
           if (!live[d]) continue;
           const bool mine = st.rk == t0 + d;
           const bool ins_t = MODE == MODE_MIXED ? st.bcast_bool(ins, t0 + d) : MODE == MODE_INSERT;
-          if (st.ballot(lane_has<S0, W0>(buf[d], ev[d]))) {
-            if (mine) { result = ins_t ? R_FOUND : 1; stage = 0; }
+          const uint32_t hits = st.ballot(lane_has<S0, W0>(buf[d], ev[d]));
+          if (hits) {
+            if constexpr (MODE == MODE_ERASE) {
+              const int f = ctz32(hits);
+              const uint32_t i = st.bcast((uint32_t)lane_match<S0, W0>(buf[d], ev[d]), f);
+              uint32_t wf = 0;
+              if constexpr (S0 == 16) wf = st.bcast(get_word<W0>(buf[d], (int)(i >> 1)), f);
+              if (mine) { erase = true; q = (uint32_t)(f * PER0) + i; word = wf; stage = 0; }
+            } else {
+              if (mine) { result = ins_t ? R_FOUND : 1; stage = 0; }
+            }
             continue;
           }
           KM0 knd = 0;
-          if constexpr (MODE != MODE_FIND) knd = kn[d];
+          if constexpr (WRITES) knd = kn[d];
           const int le = lane_first_empty<S0, W0>(buf[d], ins_t ? lane_bits<PER0>(knd, st.rk * PER0) : 0u);
           const uint32_t em = st.ballot(le < PER0);
           if (!em) {
@@ -129,13 +143,16 @@ __device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, 
           if (mine) { claim = true; q = (uint32_t)(f * PER0) + lef; word = wf; }
         }
       }
-      if constexpr (MODE != MODE_FIND) {
+      if constexpr (WRITES) {
         if (claim) {
           const int r = claim_at<S0>(L0.base + s0.a * L0.bucket_words, q, word, s0.e);
           if (r == CLAIM_WON) { result = R_PUT; stage = 0; }
           else if (r == CLAIM_SAME) { result = R_FOUND; stage = 0; }
           else known0 |= (KM0)1 << q;
         }
+      }
+      if constexpr (MODE == MODE_ERASE) {
+        if (erase) result = erase_at<S0>(L0.base + s0.a * L0.bucket_words, q, word, s0.e) ? 1 : 0;
       }
     }
     // ------------------------------------------------------------ level 2
@@ -145,7 +162,7 @@ __device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, 
         s2 = split_key<U, S1>(T, L1, 2, k, 1u);
         have12 = true;
       }
-      bool claim = false;
+      bool claim = false, erase = false;
       uint32_t q = 0, word = 0, pick2 = 0;
 #pragma unroll 1
       for (int t0 = 0; t0 < G; t0 += D1) {
@@ -160,7 +177,7 @@ __device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, 
           const uint32_t a2 = st.bcast((uint32_t)s2.a, t0 + d);
           const uint64_t e1 = st.template bcast_slot<S1>(s1.e, t0 + d);
           const uint64_t e2 = st.template bcast_slot<S1>(s2.e, t0 + d);
-          if constexpr (MODE != MODE_FIND) {
+          if constexpr (WRITES) {
             const KM1 k1 = st.bcast_mask(known1, t0 + d);
             const KM1 k2 = st.bcast_mask(known2, t0 + d);
             kn[d] = half ? k2 : k1;
@@ -174,8 +191,24 @@ __device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, 
           if (!live[d]) continue;
           const bool mine = st.rk == t0 + d;
           const bool ins_t = MODE == MODE_MIXED ? st.bcast_bool(ins, t0 + d) : MODE == MODE_INSERT;
-          if (st.ballot(lane_has<S1, W1>(buf[d], ev[d]))) {
-            if (mine) { result = ins_t ? R_FOUND : 1; stage = 0; }
+          const uint32_t hits = st.ballot(lane_has<S1, W1>(buf[d], ev[d]));
+          if (hits) {
+            if constexpr (MODE == MODE_ERASE) {
+              // lanes [0, HG) read secondary bucket 1, lanes [HG, G) bucket 2
+              const int f = ctz32(hits);
+              const uint32_t i = st.bcast((uint32_t)lane_match<S1, W1>(buf[d], ev[d]), f);
+              uint32_t wf = 0;
+              if constexpr (S1 == 16) wf = st.bcast(get_word<W1>(buf[d], (int)(i >> 1)), f);
+              if (mine) {
+                erase = true;
+                pick2 = f >= HG ? 1u : 0u;
+                q = (uint32_t)((f & (HG - 1)) * PER1) + i;
+                word = wf;
+                stage = 0;
+              }
+            } else {
+              if (mine) { result = ins_t ? R_FOUND : 1; stage = 0; }
+            }
             continue;
           }
           if (!ins_t) {
@@ -183,7 +216,7 @@ __device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, 
             continue;
           }
           KM1 knd = 0;
-          if constexpr (MODE != MODE_FIND) knd = kn[d];
+          if constexpr (WRITES) knd = kn[d];
           const int le = lane_first_empty<S1, W1>(buf[d], lane_bits<PER1>(knd, hr * PER1));
           const uint32_t em = st.ballot(le < PER1);
           const uint32_t em1 = em & hmask, em2 = em >> HG;
@@ -202,7 +235,14 @@ __device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, 
           if (mine) { claim = true; q = lp; word = wf; pick2 = p1 ? 0u : 1u; }
         }
       }
-      if constexpr (MODE != MODE_FIND) {
+      if constexpr (MODE == MODE_ERASE) {
+        if (erase) {
+          const uint64_t ab = pick2 ? s2.a : s1.a;
+          const uint64_t e = pick2 ? s2.e : s1.e;
+          result = erase_at<S1>(L1.base + ab * L1.bucket_words, q, word, e) ? 1 : 0;
+        }
+      }
+      if constexpr (WRITES) {
         if (claim) {
           const uint64_t ab = pick2 ? s2.a : s1.a;
           const uint64_t e = pick2 ? s2.e : s1.e;

@@ -13,14 +13,14 @@ struct IceVariant {
   int key64;           // 1: 64-bit key words
   int S0, S1, B0, B1;  // slot bits and bucket slots per level
   int G;               // sub-tile lanes
-  launch_fn find, insert, mixed;
+  launch_fn find, insert, mixed, erase;
   multi_fn multi_find, multi_insert;
 };
 
 struct CkVariant {
   int key64;
   int S, B, G;
-  launch_fn put, find;
+  launch_fn put, find, erase;
   multi_fn multi_put, multi_find;
 };
 

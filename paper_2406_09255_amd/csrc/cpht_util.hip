@@ -6,9 +6,10 @@
 
 namespace cpht {
 
-// Count non-EMPTY slots of S bits in a level of `words` 32-bit words.  Each
-// thread streams 16-byte pieces (grid-stride), the block reduces through
-// LDS and adds its total to *count with one atomic.
+// Count the slots of S bits that hold a key (occupancy bit, the top bit of
+// the slot, set; EMPTY and tombstones have it clear) in a level of `words`
+// 32-bit words.  Each thread streams 16-byte pieces (grid-stride), the block
+// reduces through LDS and adds its total to *count with one atomic.
 template <int S>
 __global__ __launch_bounds__(256) void count_kernel(const uint32_t* base, uint64_t words,
                                                     unsigned long long* count) {
@@ -22,18 +23,18 @@ __global__ __launch_bounds__(256) void count_kernel(const uint32_t* base, uint64
     const uint32_t q[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      if constexpr (S == 16) c += ((q[j] & 0xFFFFu) != 0u) + ((q[j] >> 16) != 0u);
-      else if constexpr (S == 32) c += q[j] != 0u;
-      else if (j % 2 == 0) c += (q[j] | q[j + 1]) != 0u;
+      if constexpr (S == 16) c += ((q[j] >> 15) & 1u) + (q[j] >> 31);
+      else if constexpr (S == 32) c += q[j] >> 31;
+      else if (j % 2 == 1) c += q[j] >> 31;  // high word of a 64-bit slot
     }
   }
   // tail words (levels smaller than 16 bytes or not a multiple of 4 words)
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     for (uint64_t i = nvec * 4; i < words; ++i) {
       const uint32_t q = base[i];
-      if constexpr (S == 16) c += ((q & 0xFFFFu) != 0u) + ((q >> 16) != 0u);
-      else if constexpr (S == 32) c += q != 0u;
-      else if ((i & 1) == 0) c += (q | base[i + 1]) != 0u;
+      if constexpr (S == 16) c += ((q >> 15) & 1u) + (q >> 31);
+      else if constexpr (S == 32) c += q >> 31;
+      else if ((i & 1) == 1) c += q >> 31;
     }
   }
   unsigned long long s = c;

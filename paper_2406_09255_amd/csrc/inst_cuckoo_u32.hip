@@ -4,17 +4,17 @@
 
 namespace cpht {
 namespace {
-template <int S, int B, int G, bool PUT>
+template <int S, int B, int G, int OP>
 void launch(const TableK& T, const BatchK& Bt, hipStream_t s) {
-  launch_grid(cuckoo_kernel<uint32_t, S, B, G, PUT>, T, Bt, s);
+  launch_grid(cuckoo_kernel<uint32_t, S, B, G, OP>, T, Bt, s);
 }
-template <int S, int B, int G, bool PUT>
+template <int S, int B, int G, int OP>
 void launch_multi(const MultiK& M, uint32_t blocks, hipStream_t s) {
-  launch_chunks(cuckoo_multi_kernel<uint32_t, S, B, G, PUT>, M, blocks, s);
+  launch_chunks(cuckoo_multi_kernel<uint32_t, S, B, G, OP>, M, blocks, s);
 }
 #define CPHT_CK_ENTRY(S, B, G) \
-  {0, S, B, G, &launch<S, B, G, true>, &launch<S, B, G, false>, \
-   &launch_multi<S, B, G, true>, &launch_multi<S, B, G, false>},
+  {0, S, B, G, &launch<S, B, G, CK_PUT>, &launch<S, B, G, CK_FIND>, &launch<S, B, G, CK_ERASE>, \
+   &launch_multi<S, B, G, CK_PUT>, &launch_multi<S, B, G, CK_FIND>},
 const CkVariant kList[] = {CPHT_CK_LIST(CPHT_CK_ENTRY)};
 }  // namespace
 

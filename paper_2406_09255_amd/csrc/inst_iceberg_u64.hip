@@ -15,6 +15,7 @@ void launch_multi(const MultiK& M, uint32_t blocks, hipStream_t s) {
 #define CPHT_ICE_ENTRY(S0, S1, B0, G) \
   {1, S0, S1, B0, B0 / 2, G, &launch<S0, S1, B0, B0 / 2, G, MODE_FIND>, \
    &launch<S0, S1, B0, B0 / 2, G, MODE_INSERT>, &launch<S0, S1, B0, B0 / 2, G, MODE_MIXED>, \
+   &launch<S0, S1, B0, B0 / 2, G, MODE_ERASE>, \
    &launch_multi<S0, S1, B0, B0 / 2, G, MODE_FIND>, &launch_multi<S0, S1, B0, B0 / 2, G, MODE_INSERT>},
 const IceVariant kList[] = {CPHT_ICE_LIST(CPHT_ICE_ENTRY)};
 }  // namespace

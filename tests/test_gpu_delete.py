@@ -1,0 +1,128 @@
+"""GPU parity of delete by tombstone (Sec. 2.2 "Lookup", Sec. 3
+"Limitations") against the oracle, for both schemes.
+
+Which of several deletes of the same key in one batch answers 1 depends on
+timing, so answers are compared per distinct key (exactly one 1 for a stored
+key, none for an absent one); everything after the batch is unique and is
+compared exactly: the decoded key set, every lookup, the occupied count, and
+the number of tombstones.  The checker accepts tombstones and still requires
+non-empty slots to form a prefix and the order / early-exit invariants.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2406_09255_amd as cpht
+import synth
+from oracle import sets
+from tests.helpers import check_table, host_u64, images, oracle_table, to_dev
+
+pytestmark = pytest.mark.gpu
+
+KEY_SEED = 0xDE1E7E
+
+
+def _tombs(t: cpht.Table) -> int:
+    n = 0
+    for x, img in enumerate(images(t)):
+        s = t.config.slot_bits0 if x == 0 else t.config.slot_bits1
+        dt = {16: np.uint16, 32: np.uint32, 64: np.uint64}[s]
+        n += int((img.view(dt) == 1).sum())
+    return n
+
+
+def _per_key(keys_h, ans):
+    u, inv = np.unique(keys_h, return_inverse=True)
+    tot = np.zeros(u.size, np.int64)
+    np.add.at(tot, inv.reshape(-1), ans.astype(np.int64))
+    return u, tot
+
+
+def _dev(keys_h, w, gpu):
+    return to_dev(torch.from_numpy(keys_h.astype(np.int64)), w, gpu)
+
+
+SHAPES = [
+    ("cuckoo", dict(scheme=cpht.CUCKOO, key_bits=32, log2_slots0=14, bucket0=32, slot_bits0=32)),
+    ("cuckoo64", dict(scheme=cpht.CUCKOO, key_bits=37, log2_slots0=14, bucket0=16, slot_bits0=64, compact=0)),
+    ("ice16", dict(scheme=cpht.ICEBERG, key_bits=22, log2_slots0=16, log2_slots1=13, bucket0=32, bucket1=16,
+                   slot_bits0=16, slot_bits1=16)),
+    ("ice16_32", dict(scheme=cpht.ICEBERG, key_bits=28, log2_slots0=18, log2_slots1=15, bucket0=32, bucket1=16,
+                      slot_bits0=16, slot_bits1=32)),
+    ("ice64", dict(scheme=cpht.ICEBERG, key_bits=40, log2_slots0=14, log2_slots1=11, bucket0=16, bucket1=8,
+                   slot_bits0=64, slot_bits1=64, compact=0)),
+]
+
+
+@pytest.mark.parametrize("name,kw", SHAPES, ids=[s[0] for s in SHAPES])
+def test_delete_matches_oracle(gpu, name, kw):
+    t = cpht.Table(seed=0xD0 + len(name), **kw)
+    o = oracle_table(t)
+    w = t.config.key_bits
+    cap = t.count()[1]
+    # fill to 0.7 (the iceberg primary overflows into the secondaries); the
+    # tombstones keep their slots, so the later inserts stay below 0.85
+    n = int(0.7 * cap)
+    keys = synth.distinct_keys(w, KEY_SEED, 0, n)
+    kh = host_u64(keys)
+    assert (t.insert(to_dev(keys, w, gpu)) == cpht.PUT).all()
+    assert (o.insert(kh) == oracle.PUT).all()
+    S = np.sort(kh)
+    rng = np.random.default_rng(len(name))
+    # deletes: 25 % of the stored keys, a quarter of them twice, plus absent keys
+    gone = kh[rng.permutation(n)[: int(0.25 * n)]]
+    absent = host_u64(synth.distinct_keys(w, KEY_SEED, n, 3000))
+    batch = np.concatenate([gone, gone[: gone.size // 4], absent])
+    batch = batch[rng.permutation(batch.size)]
+    got = t.delete(_dev(batch, w, gpu)).cpu().numpy()
+    want_first, S = sets.delete(S, batch)
+    assert np.array_equal(o.delete(batch), want_first)
+    u, g = _per_key(batch, got)
+    _, wnt = _per_key(batch, want_first)
+    assert np.array_equal(g, wnt), f"{int((g != wnt).sum())} keys answered differently"
+    assert np.array_equal(check_table(t), S)
+    assert t.count()[0] == S.size == o.occupied()
+    assert _tombs(t) == o.tombstones() == gone.size
+    q = np.concatenate([kh, absent])
+    assert np.array_equal(t.find(_dev(q, w, gpu)).cpu().numpy(), o.find(q))
+
+    # after the deletes: cuckoo puts fresh keys (evictions may land on
+    # tombstones); iceberg find-or-puts deleted and fresh keys again
+    fresh = host_u64(synth.distinct_keys(w, KEY_SEED, n + 3000, int(0.04 * cap)))
+    if t.config.scheme == cpht.CUCKOO:
+        add = fresh
+        got2 = t.insert(_dev(add, w, gpu)).cpu().numpy()
+        assert (got2 == cpht.PUT).all()
+        assert (o.insert(add) == oracle.PUT).all()
+    else:
+        add = np.concatenate([gone[: gone.size // 4], fresh])
+        add = add[rng.permutation(add.size)]
+        got2 = t.insert(_dev(add, w, gpu)).cpu().numpy()
+        want2 = o.insert(add)
+        assert (got2 != cpht.FULL).all() and (want2 != oracle.FULL).all()
+        ok, msg = sets.check_insert_outcomes(S, add, got2)
+        assert ok, msg
+    S = np.union1d(S, add)
+    assert np.array_equal(check_table(t), S)
+    assert t.count()[0] == S.size == o.occupied()
+    assert np.array_equal(t.find(_dev(q, w, gpu)).cpu().numpy(), o.find(q))
+
+
+def test_delete_edge_cases(gpu):
+    t = cpht.Table(scheme=cpht.ICEBERG, key_bits=32, log2_slots0=12, log2_slots1=9, bucket0=32, bucket1=16,
+                   slot_bits0=32, slot_bits1=32)
+    k = torch.arange(1, 1001, dtype=torch.int32, device=gpu)
+    assert int(t.delete(k).sum().item()) == 0  # empty table
+    assert t.delete(k[:0]).numel() == 0
+    t.insert(k)
+    same = torch.full((5000,), 7, dtype=torch.int32, device=gpu)
+    assert int(t.delete(same).sum().item()) == 1  # one of the 5000 removes it
+    assert t.count()[0] == 999
+    assert int(t.find(k).sum().item()) == 999
+    assert int(t.delete(k).sum().item()) == 999
+    assert t.count()[0] == 0 and _tombs(t) == 1000
+    t.clear()
+    assert _tombs(t) == 0 and t.count()[0] == 0
