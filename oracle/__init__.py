@@ -59,6 +59,8 @@ class Cfg(ctypes.Structure):
         ("H", ctypes.c_uint32),
         ("C", ctypes.c_uint32),
         ("compact", ctypes.c_uint32),
+        ("log2_lists", ctypes.c_uint32),
+        ("pool_slabs", ctypes.c_uint32),
         ("pad", ctypes.c_uint32),
         ("seed", ctypes.c_uint64),
     ]
@@ -113,6 +115,10 @@ def lib():
         L.or_export.argtypes = [vp, i32, vp, u64]
         L.or_check.restype = i32
         L.or_check.argtypes = [ctypes.POINTER(Cfg), vp, vp, vp, ctypes.POINTER(u64), ctypes.c_char_p, i32]
+        L.or_check3.restype = i32
+        L.or_check3.argtypes = [ctypes.POINTER(Cfg), vp, vp, vp, vp, vp, ctypes.POINTER(u64), ctypes.c_char_p, i32]
+        L.or_l3_used.restype = ctypes.c_uint32
+        L.or_l3_used.argtypes = [vp]
         L.or_bucket_of.restype = u64
         L.or_bucket_of.argtypes = [vp, i32, u32, u64]
         L.or_stored_form.restype = u64
@@ -199,10 +205,10 @@ class Table:
     """A host-memory table driven one operation at a time."""
 
     def __init__(self, scheme, w, log2_slots0, B0, s0, log2_slots1=0, B1=0, s1=32,
-                 H=2, C=256, compact=True, seed=1):
+                 H=2, C=256, compact=True, seed=1, log2_lists=0, pool_slabs=0):
         self.cfg = Cfg(scheme=scheme, w=w, log2_slots0=log2_slots0, log2_slots1=log2_slots1,
-                       B0=B0, B1=B1, s0=s0, s1=s1, H=H, C=C, compact=int(compact), pad=0,
-                       seed=seed & (2**64 - 1))
+                       B0=B0, B1=B1, s0=s0, s1=s1, H=H, C=C, compact=int(compact), log2_lists=log2_lists,
+                       pool_slabs=pool_slabs, pad=0, seed=seed & (2**64 - 1))
         self._h = lib().or_new(ctypes.byref(self.cfg))
         if not self._h:
             raise ValueError("oracle rejected the table configuration")
@@ -277,13 +283,21 @@ class Table:
             raise ValueError("bad permutation index")
         return a, e
 
+    def l3_used(self) -> int:
+        """Slabs of the third level handed out so far."""
+        return int(lib().or_l3_used(self._h))
+
     def check(self):
         imgs = [self.export(x) for x in range(self.nlevels)]
+        if self.cfg.pool_slabs:
+            imgs += [self.export(2), self.export(3)]
         return check_images(self.cfg, *imgs)
 
 
-def check_images(cfg: Cfg, img0: np.ndarray, img1: np.ndarray | None = None):
-    """Run the table checker over raw level images.
+def check_images(cfg: Cfg, img0: np.ndarray, img1: np.ndarray | None = None, pool: np.ndarray | None = None,
+                 heads: np.ndarray | None = None):
+    """Run the table checker over raw level images (`pool` and `heads`: the
+    third level's slab pool and list heads, when the table has one).
 
     Returns (ok, message, sorted decoded key array)."""
     img0 = np.ascontiguousarray(img0, dtype=np.uint8)
@@ -291,11 +305,16 @@ def check_images(cfg: Cfg, img0: np.ndarray, img1: np.ndarray | None = None):
     if img1 is not None:
         img1 = np.ascontiguousarray(img1, dtype=np.uint8)
         cap += img1.size * 8 // max(1, cfg.s1)
+    if pool is not None:
+        pool = np.ascontiguousarray(pool, dtype=np.uint8)
+        heads = np.ascontiguousarray(heads, dtype=np.uint8)
+        cap += pool.size * 8 // 32
     keys = np.zeros(max(1, cap), np.uint64)
     nk = ctypes.c_uint64(0)
     msg = ctypes.create_string_buffer(512)
-    rc = lib().or_check(ctypes.byref(cfg), _ptr(img0), _ptr(img1) if img1 is not None else None,
-                        _ptr(keys), ctypes.byref(nk), msg, 512)
+    rc = lib().or_check3(ctypes.byref(cfg), _ptr(img0), _ptr(img1) if img1 is not None else None,
+                         _ptr(pool) if pool is not None else None, _ptr(heads) if heads is not None else None,
+                         _ptr(keys), ctypes.byref(nk), msg, 512)
     if rc < 0:
         raise ValueError("checker rejected the configuration")
     return rc == 0, msg.value.decode(), keys[: nk.value].copy()

@@ -30,6 +30,10 @@
  *   5. Iceberg lookup (Sec. 2.3 "Lookup", levels 1 and 2).
  *   6. Compact cuckoo put (Sec. 4.4, Alg. 4) and lookup (Sec. 4.4 "Lookup").
  *   6b. Delete by tombstone, both schemes.
+ *   4b. The third iceberg level (Sec. 2.3: linked lists outside the table,
+ *      the list chosen by h_0(k)): lists of 128-byte slabs taken from a
+ *      fixed pool; a key goes there only when its primary bucket and both
+ *      secondary buckets are full.
  *   7. A table checker for raw table images (well-formedness and the order
  *      property of Appendix A Definition 2, no duplicates (Lemma 1), prefix
  *      filling, and the cuckoo early-exit invariant of Sec. 2.2 / 4.4).
@@ -171,6 +175,8 @@ typedef struct {
     uint32_t H;            /* cuckoo hash functions (2..3) */
     uint32_t C;            /* cuckoo eviction chain bound */
     uint32_t compact;      /* 1: store remainders; 0: store the full pi(k) */
+    uint32_t log2_lists;   /* iceberg level 3: number of lists (log2) */
+    uint32_t pool_slabs;   /* iceberg level 3: slabs in the pool; 0 = two levels only */
     uint32_t pad;
     uint64_t seed;
 } or_cfg_t;
@@ -185,10 +191,26 @@ typedef struct {
     uint64_t* slot;   /* one 64-bit word per slot, holding the s-bit value */
 } or_level_t;
 
+/* Level 3: 2^log2_lists lists, each a chain of slabs of 128 bytes.  A slab
+ * has B slots of s bits (s = 32, or 64 for 64-bit primary slots); its last
+ * slot holds the id of the next slab (0 = end of list).  Slab ids count from
+ * 1; slab id sits at pool position id - 1.  Addressing and encoding are a
+ * level's: the list is the high log2_lists bits of pi_0(k), the stored form
+ * the occupancy bit and the remaining bits (all w bits if not compact). */
+typedef struct {
+    int on;
+    or_level_t L;      /* nb = log2_lists, B = slots per slab, slot = the pool */
+    uint64_t nlists;
+    uint32_t nslabs;   /* pool capacity */
+    uint32_t used;     /* slabs handed out so far */
+    uint64_t* head;    /* first slab id of each list */
+} or_l3_t;
+
 typedef struct {
     or_cfg_t cfg;
     or_perm_t perm[3];
     or_level_t lv[2];
+    or_l3_t l3;
     int nlevels;
     uint32_t line_bytes;
 } or_table_t;
@@ -244,6 +266,26 @@ or_table_t* or_new(const or_cfg_t* c)
     } else if (c->scheme == OR_ICEBERG) {
         err = level_init(&t->lv[0], c, c->log2_slots0, c->B0, c->s0, 0);
         if (!err) err = level_init(&t->lv[1], c, c->log2_slots1, c->B1, c->s1, 1);
+        if (!err && c->pool_slabs > 0) {
+            or_l3_t* q = &t->l3;
+            uint32_t s3 = c->s0 == 64 ? 64 : 32;
+            uint32_t b3 = 1024 / s3;
+            q->L.B = b3;
+            q->L.s = s3;
+            q->L.nb = c->log2_lists;
+            q->L.pbits = c->compact ? c->w - c->log2_lists : c->w;
+            q->L.tbits = 0;
+            if (c->log2_lists > c->w || c->log2_lists > 30 || q->L.pbits + 1 > s3) err = -1;
+            if (!err) {
+                q->L.nslots = (uint64_t)c->pool_slabs * b3;
+                q->L.slot = (uint64_t*)calloc(q->L.nslots, sizeof(uint64_t));
+                q->nlists = 1ULL << c->log2_lists;
+                q->head = (uint64_t*)calloc(q->nlists, sizeof(uint64_t));
+                q->nslabs = c->pool_slabs;
+                q->on = 1;
+                if (!q->L.slot || !q->head) err = -2;
+            }
+        }
         t->nlevels = 2;
         for (uint32_t j = 0; j < 3; ++j) or_perm_init(&t->perm[j], c->w, c->seed, j);
     } else {
@@ -252,6 +294,8 @@ or_table_t* or_new(const or_cfg_t* c)
     if (err) {
         free(t->lv[0].slot);
         free(t->lv[1].slot);
+        free(t->l3.L.slot);
+        free(t->l3.head);
         free(t);
         return NULL;
     }
@@ -263,6 +307,8 @@ void or_free(or_table_t* t)
     if (!t) return;
     free(t->lv[0].slot);
     free(t->lv[1].slot);
+    free(t->l3.L.slot);
+    free(t->l3.head);
     free(t);
 }
 
@@ -373,6 +419,55 @@ static uint64_t* ice_slot(or_table_t* t, const or_ice_key_t* q, uint32_t x, uint
     return bucket_ptr(L, q->a[x]) + y;
 }
 
+/* ---- 4b. Level 3 ---------------------------------------------------- */
+
+static uint64_t* l3_slab(or_table_t* t, uint64_t id) { return t->l3.L.slot + (id - 1) * t->l3.L.B; }
+
+/* Find-or-put in k's list: slots in list order (slab by slab, slot by slot);
+ * k's stored form before the first empty slot -> FOUND, else the first empty
+ * slot takes it -> PUT; a full last slab gets a new slab from the pool, FULL
+ * when the pool is used up. */
+static int l3_fop(or_table_t* t, uint64_t k, uint32_t* lines)
+{
+    or_level_t* L = &t->l3.L;
+    const uint64_t e = enc_of(t, L, 0, k, 0);
+    const uint32_t nslot = L->B - 1;
+    uint64_t* link = &t->l3.head[addr_of(t, L, 0, k)];
+    for (;;) {
+        if (*link == 0) {
+            if (t->l3.used == t->l3.nslabs) return OR_FULL;
+            *link = ++t->l3.used;
+        }
+        uint64_t* sb = l3_slab(t, *link);
+        if (lines) ++*lines;
+        for (uint32_t i = 0; i < nslot; ++i) {
+            if (sb[i] == e) return OR_FOUND;
+            if (sb[i] == 0) { sb[i] = e; return OR_PUT; }
+        }
+        link = &sb[nslot];
+    }
+}
+
+/* The slot of k's list holding k's stored form, or NULL (the walk stops at
+ * an empty slot: slots fill in list order). */
+static uint64_t* l3_lookup(or_table_t* t, uint64_t k, uint32_t* lines)
+{
+    or_level_t* L = &t->l3.L;
+    const uint64_t e = enc_of(t, L, 0, k, 0);
+    const uint32_t nslot = L->B - 1;
+    uint64_t id = t->l3.head[addr_of(t, L, 0, k)];
+    while (id) {
+        uint64_t* sb = l3_slab(t, id);
+        if (lines) ++*lines;
+        for (uint32_t i = 0; i < nslot; ++i) {
+            if (sb[i] == e) return &sb[i];
+            if (sb[i] == 0) return NULL;
+        }
+        id = sb[nslot];
+    }
+    return NULL;
+}
+
 /* One find-or-put, sequentially (Alg. 5): look at every slot of the key's
  * three buckets; if one holds r'_x(k) the result is FOUND; if none is empty
  * the result is FULL; otherwise write r'_x(k) into the least empty slot under
@@ -403,7 +498,8 @@ static int ice_fop_one(or_table_t* t, uint64_t k, const uint32_t* ox, const uint
             return OR_PUT;
         }
     }
-    return OR_FULL;
+    /* all three buckets full without k: the third level, if there is one */
+    return t->l3.on ? l3_fop(t, k, lines) : OR_FULL;
 }
 
 /* Iceberg lookup (Sec. 2.3 "Lookup", levels 1 and 2): the primary bucket
@@ -422,10 +518,16 @@ static int ice_find_one(or_table_t* t, uint64_t k, uint32_t* lines)
     }
     if (has_empty) return 0;
     if (lines) *lines += 2 * bucket_lines(t, &t->lv[1]);
+    int room = 0;
     for (uint32_t x = 1; x <= 2; ++x)
-        for (uint32_t y = 0; y < t->cfg.B1; ++y)
-            if (*ice_slot(t, &q, x, y) == q.e[x]) return 1;
-    return 0;
+        for (uint32_t y = 0; y < t->cfg.B1; ++y) {
+            uint64_t v = *ice_slot(t, &q, x, y);
+            if (v == q.e[x]) return 1;
+            if (v == 0) room = 1;
+        }
+    /* k reaches level 3 only through two full secondary buckets */
+    if (room || !t->l3.on) return 0;
+    return l3_lookup(t, k, lines) != NULL;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -517,6 +619,10 @@ static int del_one(or_table_t* t, uint64_t k)
                 if (*s == q.e[x]) { *s = OR_TOMB; return 1; }
             }
         }
+        if (t->l3.on) {
+            uint64_t* s = l3_lookup(t, k, NULL);
+            if (s) { *s = OR_TOMB; return 1; }
+        }
         return 0;
     }
     or_level_t* L = &t->lv[0];
@@ -591,6 +697,8 @@ uint64_t or_occupied(const or_table_t* t)
     uint64_t c = 0;
     for (int x = 0; x < t->nlevels; ++x)
         for (uint64_t i = 0; i < t->lv[x].nslots; ++i) c += (uint64_t)holds_key(&t->lv[x], t->lv[x].slot[i]);
+    if (t->l3.on)  /* link slots hold slab ids < 2^31: never an occupancy bit */
+        for (uint64_t i = 0; i < t->l3.L.nslots; ++i) c += (uint64_t)holds_key(&t->l3.L, t->l3.L.slot[i]);
     return c;
 }
 
@@ -600,8 +708,14 @@ uint64_t or_tombstones(const or_table_t* t)
     uint64_t c = 0;
     for (int x = 0; x < t->nlevels; ++x)
         for (uint64_t i = 0; i < t->lv[x].nslots; ++i) c += t->lv[x].slot[i] == OR_TOMB;
+    if (t->l3.on)
+        for (uint64_t i = 0; i < t->l3.L.nslots; ++i)
+            c += (i % t->l3.L.B != t->l3.L.B - 1) && t->l3.L.slot[i] == OR_TOMB;
     return c;
 }
+
+/* Slabs of level 3 handed out so far. */
+uint32_t or_l3_used(const or_table_t* t) { return t->l3.used; }
 
 uint64_t or_capacity(const or_table_t* t)
 {
@@ -610,19 +724,35 @@ uint64_t or_capacity(const or_table_t* t)
     return c;
 }
 
+/* Raw images: level 0 primary, level 1 secondary, level 2 the level-3
+ * slab pool (pool_slabs x 128 bytes, slot layout as the other levels, the
+ * last slot of a slab holding the next slab id), level 3 the list heads
+ * (one little-endian uint32 slab id per list). */
+static or_level_t* image_level(or_table_t* t, int level)
+{
+    if (level >= 0 && level < t->nlevels) return &t->lv[level];
+    if (level == 2 && t->l3.on) return &t->l3.L;
+    return NULL;
+}
+
 uint64_t or_level_bytes(const or_table_t* t, int level)
 {
-    if (level < 0 || level >= t->nlevels) return 0;
-    return t->lv[level].nslots * t->lv[level].s / 8;
+    if (level == 3) return t->l3.on ? t->l3.nlists * 4 : 0;
+    const or_level_t* L = image_level((or_table_t*)t, level);
+    return L ? L->nslots * L->s / 8 : 0;
 }
 
 /* Write level `level` into dst as a raw image (layout in the file header). */
 int or_export(const or_table_t* t, int level, void* dst, uint64_t bytes)
 {
-    if (level < 0 || level >= t->nlevels) return -1;
-    const or_level_t* L = &t->lv[level];
-    if (bytes != L->nslots * L->s / 8) return -1;
     uint8_t* d = (uint8_t*)dst;
+    if (bytes != or_level_bytes(t, level) || bytes == 0) return -1;
+    if (level == 3) {
+        for (uint64_t h = 0; h < t->l3.nlists; ++h)
+            for (uint32_t byte = 0; byte < 4; ++byte) d[h * 4 + byte] = (uint8_t)(t->l3.head[h] >> (8 * byte));
+        return 0;
+    }
+    const or_level_t* L = image_level((or_table_t*)t, level);
     uint32_t sb = L->s / 8;
     for (uint64_t i = 0; i < L->nslots; ++i)
         for (uint32_t byte = 0; byte < sb; ++byte) d[i * sb + byte] = (uint8_t)(L->slot[i] >> (8 * byte));
@@ -632,8 +762,16 @@ int or_export(const or_table_t* t, int level, void* dst, uint64_t bytes)
 /* Load a raw image into level `level` (used by the checker). */
 static int import_level(or_table_t* t, int level, const void* src)
 {
-    or_level_t* L = &t->lv[level];
     const uint8_t* s = (const uint8_t*)src;
+    if (level == 3) {
+        for (uint64_t h = 0; h < t->l3.nlists; ++h) {
+            uint64_t v = 0;
+            for (uint32_t byte = 0; byte < 4; ++byte) v |= (uint64_t)s[h * 4 + byte] << (8 * byte);
+            t->l3.head[h] = v;
+        }
+        return 0;
+    }
+    or_level_t* L = image_level(t, level);
     uint32_t sb = L->s / 8;
     for (uint64_t i = 0; i < L->nslots; ++i) {
         uint64_t v = 0;
@@ -668,15 +806,21 @@ static int cmp_u64(const void* a, const void* b)
  *   - cuckoo: a key stored under hash j > 0 has a full bucket a_{j-1}(k)
  *     (the invariant the early-exit lookup relies on, Sec. 2.2 / 4.4).
  * Returns 0 if all hold, 1 with a message otherwise, <0 on bad arguments. */
-int or_check(const or_cfg_t* c, const void* img0, const void* img1, uint64_t* keys_out,
-             uint64_t* n_keys, char* msg, int msglen)
+int or_check3(const or_cfg_t* c, const void* img0, const void* img1, const void* pool, const void* heads,
+              uint64_t* keys_out, uint64_t* n_keys, char* msg, int msglen)
 {
     int rc = 0;
     uint64_t nk = 0;
+    uint8_t* seen = NULL;
     or_table_t* t = or_new(c);
     if (!t) return -1;
+    if (t->l3.on && (!pool || !heads)) { or_free(t); return -1; }
     import_level(t, 0, img0);
     if (t->nlevels == 2) import_level(t, 1, img1);
+    if (t->l3.on) {
+        import_level(t, 2, pool);
+        import_level(t, 3, heads);
+    }
 
     for (int x = 0; x < t->nlevels; ++x) {
         or_level_t* L = &t->lv[x];
@@ -726,13 +870,73 @@ int or_check(const or_cfg_t* c, const void* img0, const void* img1, uint64_t* ke
             }
         }
     }
+    /* level 3: every list is a chain of distinct slabs in which slots fill in
+     * order (a slab is followed only once it is full); every stored key
+     * decodes to its own list, and its primary and both secondary buckets are
+     * full without it (level 3 comes after them in the order of Def. 1);
+     * slabs on no list (lost link races) are untouched. */
+    if (t->l3.on) {
+        or_l3_t* q3 = &t->l3;
+        or_level_t* L = &q3->L;
+        const uint32_t nslot = L->B - 1;
+        seen = (uint8_t*)calloc((size_t)q3->nslabs + 1, 1);
+        if (!seen) { rc = -2; goto done; }
+        for (uint64_t h = 0; h < q3->nlists; ++h) {
+            uint64_t id = q3->head[h];
+            int seen_empty = 0;
+            while (id) {
+                if (id > q3->nslabs) FAIL("level 3 list %llu: slab id %llu out of range", (unsigned long long)h, (unsigned long long)id);
+                if (seen[id]) FAIL("level 3 slab %llu linked twice", (unsigned long long)id);
+                if (seen_empty) FAIL("level 3 list %llu: slab %llu follows a slab with an empty slot", (unsigned long long)h, (unsigned long long)id);
+                seen[id] = 1;
+                uint64_t* sb = l3_slab(t, id);
+                for (uint32_t y = 0; y < nslot; ++y) {
+                    uint64_t v = sb[y];
+                    if (v == 0) { seen_empty = 1; continue; }
+                    if (seen_empty) FAIL("level 3 slab %llu: slot %u filled after an empty slot", (unsigned long long)id, y);
+                    if (v == OR_TOMB) continue;
+                    if (!holds_key(L, v)) FAIL("level 3 slab %llu slot %u: occupancy bit clear", (unsigned long long)id, y);
+                    if (L->pbits < L->s - 1 && (v & ~(1ULL << (L->s - 1))) >> L->pbits)
+                        FAIL("level 3 slab %llu slot %u: stray high bits", (unsigned long long)id, y);
+                    uint64_t k = dec_of(t, L, 0, h, v);
+                    if (addr_of(t, L, 0, k) != h) FAIL("level 3 slab %llu slot %u: key belongs to another list", (unsigned long long)id, y);
+                    if (enc_of(t, L, 0, k, 0) != v) FAIL("level 3 slab %llu slot %u: stored form does not re-encode", (unsigned long long)id, y);
+                    or_ice_key_t q;
+                    ice_key(t, k, &q);
+                    for (uint32_t xx = 0; xx <= 2; ++xx) {
+                        uint32_t By = xx == 0 ? c->B0 : c->B1;
+                        for (uint32_t yy = 0; yy < By; ++yy) {
+                            uint64_t vv = *ice_slot(t, &q, xx, yy);
+                            if (vv == 0) FAIL("order property: key in level 3 but slot (%u,%u) of its buckets is empty", xx, yy);
+                            if (vv == q.e[xx]) FAIL("key in level 3 also at (%u,%u)", xx, yy);
+                        }
+                    }
+                    keys_out[nk++] = k;
+                }
+                id = sb[nslot];
+            }
+        }
+        for (uint64_t id = 1; id <= q3->nslabs; ++id) {
+            if (seen[id]) continue;
+            uint64_t* sb = l3_slab(t, id);
+            for (uint32_t y = 0; y < L->B; ++y)
+                if (sb[y]) FAIL("level 3 slab %llu is on no list but not empty", (unsigned long long)id);
+        }
+    }
     qsort(keys_out, nk, sizeof(uint64_t), cmp_u64);
     for (uint64_t i = 1; i < nk; ++i)
         if (keys_out[i] == keys_out[i - 1]) FAIL("key %llu stored twice", (unsigned long long)keys_out[i]);
 done:
     *n_keys = nk;
+    free(seen);
     or_free(t);
     return rc;
+}
+
+int or_check(const or_cfg_t* c, const void* img0, const void* img1, uint64_t* keys_out,
+             uint64_t* n_keys, char* msg, int msglen)
+{
+    return or_check3(c, img0, img1, NULL, NULL, keys_out, n_keys, msg, msglen);
 }
 
 /* Bucket of key k under permutation i at level `level` (for tests that build

@@ -37,6 +37,22 @@ constexpr int SEG = TILE / WAVES;   // items per wave within a tile
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
 
+// Blocks are handed to the 8 XCDs in turn (block b runs on XCD b mod 8).
+// Consecutive sort tiles write adjacent runs of every digit, so they are given
+// to blocks of the same XCD, where the partial cache lines at the run ends
+// merge in that XCD's L2 instead of going to memory separately.  The grid has
+// XCDS * ceil(ntiles / XCDS) blocks; the surplus ones exit.
+constexpr uint32_t XCDS = 8;
+
+__host__ __device__ inline uint32_t tile_grid(uint64_t ntiles) {
+  return (uint32_t)(((ntiles + XCDS - 1) / XCDS) * XCDS);
+}
+
+__device__ __forceinline__ uint64_t tile_of_block(uint64_t ntiles) {
+  const uint64_t per = (ntiles + XCDS - 1) / XCDS;
+  return (uint64_t)(blockIdx.x % XCDS) * per + blockIdx.x / XCDS;
+}
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
   const uint32_t lane = lane_id();
 #pragma unroll
@@ -91,10 +107,12 @@ template <class K>
 __global__ __launch_bounds__(TPB) void sort_hist(const K* __restrict__ keys, uint64_t n, uint32_t shift,
                                                  uint32_t* __restrict__ counts, uint32_t ntiles) {
   __shared__ uint32_t h[WAVES][RADIX];
+  const uint64_t tile = tile_of_block(ntiles);
+  if (tile >= ntiles) return;
   const uint32_t wv = threadIdx.x >> 6;
   for (int i = threadIdx.x; i < WAVES * RADIX; i += TPB) (&h[0][0])[i] = 0u;
   __syncthreads();
-  const uint64_t base = (uint64_t)blockIdx.x * TILE;
+  const uint64_t base = tile * TILE;
 #pragma unroll 4
   for (int r = 0; r < IPT; ++r) {
     const uint64_t i = base + (uint64_t)r * TPB + threadIdx.x;
@@ -105,7 +123,7 @@ __global__ __launch_bounds__(TPB) void sort_hist(const K* __restrict__ keys, uin
     uint32_t c = 0;
 #pragma unroll
     for (int w = 0; w < WAVES; ++w) c += h[w][d];
-    counts[(uint64_t)d * ntiles + blockIdx.x] = c;
+    counts[(uint64_t)d * ntiles + tile] = c;
   }
 }
 
@@ -126,11 +144,13 @@ __global__ __launch_bounds__(TPB) void sort_scatter(const K* __restrict__ kin, c
   __shared__ uint32_t tmp[WAVES + 1];
   __shared__ K sk[TILE];
   __shared__ uint32_t si[TILE];
+  const uint64_t tile = tile_of_block(ntiles);
+  if (tile >= ntiles) return;
   const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
   for (int i = threadIdx.x; i < WAVES * RADIX; i += TPB) (&wc[0][0])[i] = 0u;
   __syncthreads();
 
-  const uint64_t tbase = (uint64_t)blockIdx.x * TILE;
+  const uint64_t tbase = tile * TILE;
   const uint64_t seg = tbase + (uint64_t)wv * SEG;
   const uint64_t below = (1ull << lane) - 1ull;
   K key[IPT];
@@ -189,7 +209,7 @@ __global__ __launch_bounds__(TPB) void sort_scatter(const K* __restrict__ kin, c
   for (uint32_t p = threadIdx.x; p < tile_n; p += TPB) {
     const K k = sk[p];
     const uint32_t d = (uint32_t)(k >> shift) & (RADIX - 1u);
-    const uint64_t o = (uint64_t)offs[(uint64_t)d * ntiles + blockIdx.x] + (p - dstart[d]);
+    const uint64_t o = (uint64_t)offs[(uint64_t)d * ntiles + tile] + (p - dstart[d]);
     kout[o] = k;
     iout[o] = si[p];
   }
@@ -201,15 +221,21 @@ __global__ __launch_bounds__(TPB) void sort_scatter(const K* __restrict__ kin, c
 // emit(i, exclusive prefix, value).
 // ---------------------------------------------------------------------------
 
+// Items are striped over the block (item base + r * TPB + thread, so every
+// load and store of a wave is contiguous); the exclusive prefix in item order
+// combines a wave scan per round with one serial pass over the per-round,
+// per-wave totals.
 template <class P>
 __global__ __launch_bounds__(TPB) void tile_reduce(P p, uint32_t* __restrict__ psum) {
   __shared__ uint32_t tmp[WAVES + 1];
   const uint64_t n = p.count();
-  const uint64_t base = (uint64_t)blockIdx.x * TILE + (uint64_t)threadIdx.x * IPT;
+  const uint64_t base = (uint64_t)blockIdx.x * TILE + threadIdx.x;
   uint32_t s = 0;
 #pragma unroll 4
-  for (int r = 0; r < IPT; ++r)
-    if (base + r < n) s += p.value(base + r);
+  for (int r = 0; r < IPT; ++r) {
+    const uint64_t i = base + (uint64_t)r * TPB;
+    if (i < n) s += p.value(i);
+  }
   uint32_t total;
   block_excl_scan(s, tmp, &total);
   if (threadIdx.x == 0) psum[blockIdx.x] = total;
@@ -243,22 +269,33 @@ __global__ __launch_bounds__(TPB) void scan_top(uint32_t* __restrict__ psum, uin
 
 template <class P>
 __global__ __launch_bounds__(TPB) void tile_apply(P p, const uint32_t* __restrict__ pexcl) {
-  __shared__ uint32_t tmp[WAVES + 1];
+  __shared__ uint32_t tot[IPT][WAVES];
+  const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
   const uint64_t n = p.count();
-  const uint64_t base = (uint64_t)blockIdx.x * TILE + (uint64_t)threadIdx.x * IPT;
-  uint32_t v[IPT];
-  uint32_t s = 0;
+  const uint64_t base = (uint64_t)blockIdx.x * TILE + threadIdx.x;
+  uint32_t v[IPT], inc[IPT];
 #pragma unroll
   for (int r = 0; r < IPT; ++r) {
-    v[r] = base + r < n ? p.value(base + r) : 0u;
-    s += v[r];
+    const uint64_t i = base + (uint64_t)r * TPB;
+    v[r] = i < n ? p.value(i) : 0u;
+    inc[r] = wave_incl_scan(v[r]);
+    if (lane == 63) tot[r][wv] = inc[r];
   }
-  uint32_t total;
-  uint32_t e = pexcl[blockIdx.x] + block_excl_scan(s, tmp, &total);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = pexcl[blockIdx.x];
+    for (int r = 0; r < IPT; ++r)
+      for (int w = 0; w < WAVES; ++w) {
+        const uint32_t t = tot[r][w];
+        tot[r][w] = run;
+        run += t;
+      }
+  }
+  __syncthreads();
 #pragma unroll
   for (int r = 0; r < IPT; ++r) {
-    if (base + r < n) p.emit(base + r, e, v[r]);
-    e += v[r];
+    const uint64_t i = base + (uint64_t)r * TPB;
+    if (i < n) p.emit(i, tot[r][wv] + inc[r] - v[r], v[r]);
   }
 }
 
@@ -431,10 +468,10 @@ hipError_t run(const TableK& T, const CkVariant* v, int key_bits, const K* keys,
   uint32_t* iout = ia;
   for (int pass = 0; pass < passes; ++pass) {
     const uint32_t shift = 8u * (uint32_t)pass;
-    hipLaunchKernelGGL(sort_hist<K>, dim3((uint32_t)ntiles), dim3(TPB), 0, s, kin, n, shift, counts,
+    hipLaunchKernelGGL(sort_hist<K>, dim3(tile_grid(ntiles)), dim3(TPB), 0, s, kin, n, shift, counts,
                        (uint32_t)ntiles);
     run_scan(CountsScan{counts, (uint64_t)RADIX * ntiles}, (uint64_t)RADIX * ntiles, psum, nullptr, s);
-    hipLaunchKernelGGL(sort_scatter<K>, dim3((uint32_t)ntiles), dim3(TPB), 0, s, kin, iin, kout, iout, n, shift,
+    hipLaunchKernelGGL(sort_scatter<K>, dim3(tile_grid(ntiles)), dim3(TPB), 0, s, kin, iin, kout, iout, n, shift,
                        (const uint32_t*)counts, (uint32_t)ntiles);
     kin = kout;
     iin = iout;
