@@ -47,7 +47,7 @@ SECTOR = 64  # write-back unit of a modified slot (measured: 68.7 B written per 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by the
 # copy-kernel calibration factors 2.0 / 1.0), profiles/cuckoo_c2_hbm_bytes.md.
 # Valid only for the kernel sources they were taken with (hash of KERNEL_SOURCES below).
-TRAFFIC = {"csrc_sha": "87b77f4d5da3721a", "cuckoo_put": 25741440408, "cuckoo_find": 11035049786}
+TRAFFIC = {"csrc_sha": "c3ccc29ee78f954b", "cuckoo_put": 25743142708, "cuckoo_find": 11034975937}
 
 
 # The sources the profiled cuckoo kernels are compiled from.
@@ -732,13 +732,13 @@ def main():
     ap.add_argument("--no-many", action="store_true", help="skip the many-table section")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop section")
     ap.add_argument("--only", default="",
-                    help="comma list of extra sections to run beside the headline step, all others skipped: "
-                         + ",".join(SECTIONS))
+                    help="comma list of extra sections to run beside the headline step, all others skipped "
+                         "('headline' for none): " + ",".join(SECTIONS))
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.only:
-        want = set(args.only.split(","))
+        want = set(args.only.split(",")) - {"headline"}  # "headline": the headline step alone
         unknown = want - set(SECTIONS)
         if unknown:
             ap.error(f"unknown sections {sorted(unknown)}")
