@@ -116,8 +116,8 @@ class Runner:
 
 # Optional sections of the JSON line (each has a --no-<name> switch or is
 # picked with --only).
-SECTIONS = ("plain", "equal", "window", "sweep", "small", "iceberg", "fop", "delete", "many", "serving", "ceilings",
-            "cpu")
+SECTIONS = ("plain", "equal", "window", "sweep", "small", "iceberg", "fop", "delete", "level3", "many", "serving",
+            "ceilings", "cpu")
 
 # (slot bits, compact, slots per bucket) of the load sweep: compact 32-bit and
 # plain 64-bit slots at 8, 16 and 32 slots per bucket.
@@ -269,6 +269,52 @@ def deletes(torch, cpht, synth, dev, reps=3):
         ms = sum(times) / len(times)
         res[name] = {"ms": round(ms, 3), "mops": round(nd / (ms / 1000.0) / 1e6, 1), "check": "ok" if ok else "FAILED"}
         del t, keys, q, out
+    return res
+
+
+def level3(torch, cpht, synth, dev, reps=3):
+    """Third iceberg level: compact 2^27 + 2^24 slots (16/32-bit), 37-bit keys,
+    filled in one batch to load 1.0 of the bucket levels -- past the point
+    where two levels answer FULL -- with and without a pool of 2^20 slabs
+    (128 MiB, 2^12 lists); then 2^26 finds (50 % hit).  Reports FULL answers,
+    keys that went to the lists, and insert / find rates."""
+    w, L = 37, 27
+    res = {"config": "iceberg 2^27 + 2^24 slots (16/32-bit), 37-bit keys, one insert batch to load 1.0 of the "
+                     "bucket levels, then 2^26 finds 50% hit; third level: 2^12 lists, pool of 2^20 slabs"}
+    for name, extra in (("two_levels", {}), ("three_levels", dict(log2_lists=12, pool_slabs=1 << 20))):
+        t = cpht.Table(scheme=cpht.ICEBERG, key_bits=w, log2_slots0=L, log2_slots1=L - 3, bucket0=32, bucket1=16,
+                       slot_bits0=16, slot_bits1=32, seed=11, **extra)
+        cap = t.count()[1]
+        n = cap
+        keys = synth.distinct_keys(w, KEY_SEED + 13, 0, n, device=dev)
+        q = synth.find_queries(w, KEY_SEED + 13, n, N_FIND, 0.5, Q_SEED + 13, device=dev)
+        out = torch.empty(n, dtype=torch.uint8, device=dev)
+        found = torch.empty(N_FIND, dtype=torch.uint8, device=dev)
+        ti, tf = [], []
+        for rep in range(reps + 1):
+            t.clear(70 + rep)
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record()
+            t.insert(keys, out)
+            e[1].record()
+            t.find(q, found)
+            e[2].record()
+            e[2].synchronize()
+            if rep:
+                ti.append(e[0].elapsed_time(e[1]))
+                tf.append(e[1].elapsed_time(e[2]))
+        nfull = int((out == cpht.FULL).sum().item())
+        occ = t.count()[0]
+        row = {"full": nfull, "stored": occ, "fill_of_bucket_levels": round(occ / cap, 4),
+               "insert_mops": round(n / (sum(ti) / len(ti) / 1000.0) / 1e6, 1),
+               "find_mops": round(N_FIND / (sum(tf) / len(tf) / 1000.0) / 1e6, 1),
+               "hit_fraction": round(float(found.float().mean().item()), 4)}
+        if extra:
+            used = t.level3_used()
+            row["slabs_used"] = used
+            row["pool_bytes"] = t.level_bytes(2)
+        res[name] = row
+        del t, keys, q, out, found
     return res
 
 
@@ -930,6 +976,9 @@ def main():
 
     if not args.no_delete:
         res["delete"] = deletes(torch, cpht, synth, dev)
+
+    if not args.no_level3:
+        res["level3"] = level3(torch, cpht, synth, dev)
 
     if not args.no_many:
         res["many_tables"] = many_tables(torch, cpht, synth, dev)

@@ -74,6 +74,8 @@ typedef struct {
     uint32_t max_chain;    /* cuckoo: eviction rounds C before FULL */
     uint32_t subtile;      /* lanes cooperating on one bucket; 0 = default for the bucket size */
     uint32_t compact;      /* 1 = store remainders (quotienting); 0 = store the full pi_i(k) */
+    uint32_t log2_lists;   /* iceberg third level: 2^log2_lists lists (ignored if pool_slabs = 0) */
+    uint32_t pool_slabs;   /* iceberg third level: 128-byte slabs in its pool; 0 = two levels only */
     uint64_t seed;         /* seed of the permutations pi_0, pi_1, pi_2 */
 } cpht_config_t;
 
@@ -87,6 +89,23 @@ void cpht_config_default(uint32_t scheme, cpht_config_t* cfg);
  * would accept it, and the resolved configuration (subtile filled in) in
  * *resolved when resolved != NULL.  Touches no device. */
 cpht_status_t cpht_config_check(const cpht_config_t* cfg, cpht_config_t* resolved);
+
+/* Third iceberg level (pool_slabs > 0; Sec. 2.3: a third level of linked
+ * lists outside the table, the list chosen by h_0(k), so that inserts do not
+ * fail; Sec. 3 Limitations: slab lists).  A key goes there only when its
+ * primary bucket and both secondary buckets are full without it.  List a
+ * holds the keys whose pi_0(k) has high log2_lists bits a; it is a chain of
+ * 128-byte slabs taken from a pool of pool_slabs slabs allocated at create.
+ * A slab has 32-bit slots (64-bit when slot_bits0 = 64) storing the
+ * occupancy bit and the remaining w - log2_lists bits of pi_0(k) (all w bits
+ * if not compact; w - log2_lists + 1 must fit the slot); its last slot holds
+ * the id of the next slab (ids count from 1; 0 = end of list).  Slots of a
+ * list fill in list order, as in a bucket; a link is set once (reserved by
+ * CAS, then published), so find-or-put keeps one copy per key.  pool_slabs <
+ * 2^31 - 1.  Insert answers CPHT_FULL only once
+ * the pool is used up.  Lookups and deletes walk the list when both
+ * secondary buckets are full.  Not supported for 64-bit primary slots with
+ * a 32-lane sub-tile, nor in table sets (CPHT_E_UNSUPPORTED). */
 
 /* Create an empty table (synchronous: allocates and zeroes device memory).
  * Level x holds 2^log2_slots_x slots in buckets of bucket_x slots; each
@@ -174,20 +193,30 @@ cpht_status_t cpht_sorted_fop(cpht_table_t t, const void* d_keys, uint64_t n, ui
  * bytes per key with 64-bit key words, 28 with 32-bit ones). */
 cpht_status_t cpht_sorted_fop_workspace(cpht_table_t t, uint64_t n, uint64_t* bytes);
 
-/* Slots holding a key (tombstones excluded) and total slots over all levels
- * (fill factor = occupied / capacity, Sec. 2.1).  Synchronises `stream`. */
+/* Slots holding a key (tombstones excluded; third-level slots included) and
+ * total slots of the bucket levels (fill factor = occupied / capacity,
+ * Sec. 2.1; with a third level it can exceed 1).  Synchronises `stream`. */
 cpht_status_t cpht_count(cpht_table_t t, uint64_t* occupied, uint64_t* capacity, void* stream);
 
-/* Size in bytes of level `level` (0, or 1 for the iceberg secondary level). */
+/* Third level: slabs taken from the pool so far (synchronous; CPHT_E_STATE
+ * without a third level).  A slab is taken only by the insert that reserved
+ * the link it goes into, so every slab taken is on a list. */
+cpht_status_t cpht_level3_used(cpht_table_t t, uint32_t* slabs);
+
+/* Size in bytes of image `level`: 0 the (primary) bucket level, 1 the iceberg
+ * secondary level, and with a third level 2 its slab pool (pool_slabs * 128
+ * bytes) and 3 its list heads (2^log2_lists uint32 slab ids). */
 cpht_status_t cpht_level_bytes(cpht_table_t t, uint32_t level, uint64_t* bytes);
 
 /* Device pointer to level `level` (for callers that copy it themselves). */
 cpht_status_t cpht_level_ptr(cpht_table_t t, uint32_t level, void** d_ptr);
 
-/* Copy level `level` to host memory (synchronous).  Raw layout: bucket b,
+/* Copy image `level` to host memory (synchronous).  Raw layout: bucket b,
  * slot q at byte offset (b*bucket + q)*slot_bits/8, little endian; a slot is 0
- * (EMPTY) or (1 << (slot_bits-1)) | tag << p | payload, where p is the
- * payload width (key_bits - log2(#buckets), or key_bits if not compact). */
+ * (EMPTY), 1 (a tombstone) or (1 << (slot_bits-1)) | tag << p | payload, where
+ * p is the payload width (key_bits - log2(#buckets), or key_bits if not
+ * compact).  The slab pool (level 2) uses the same slot layout with slab id i
+ * at byte offset (i - 1)*128; list heads (level 3) are uint32 slab ids. */
 cpht_status_t cpht_export(cpht_table_t t, uint32_t level, void* h_dst, uint64_t bytes);
 
 /* The quotienting split of Sec. 2.4 as the table applies it: for permutation

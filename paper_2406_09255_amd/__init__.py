@@ -48,6 +48,8 @@ class Config(ctypes.Structure):
         ("max_chain", ctypes.c_uint32),
         ("subtile", ctypes.c_uint32),
         ("compact", ctypes.c_uint32),
+        ("log2_lists", ctypes.c_uint32),
+        ("pool_slabs", ctypes.c_uint32),
         ("seed", ctypes.c_uint64),
     ]
 
@@ -75,6 +77,7 @@ _SIGNATURES = {
     "cpht_sorted_fop_workspace": (_I32, [_VP, _U64, ctypes.POINTER(_U64)]),
     "cpht_count": (_I32, [_VP, ctypes.POINTER(_U64), ctypes.POINTER(_U64), _VP]),
     "cpht_level_bytes": (_I32, [_VP, _U32, ctypes.POINTER(_U64)]),
+    "cpht_level3_used": (_I32, [_VP, ctypes.POINTER(_U32)]),
     "cpht_level_ptr": (_I32, [_VP, _U32, ctypes.POINTER(_VP)]),
     "cpht_export": (_I32, [_VP, _U32, _VP, _U64]),
     "cpht_split": (_I32, [_VP, _U32, _VP, _U64, _VP, _VP, _VP]),
@@ -223,6 +226,17 @@ class Table:
     @property
     def nlevels(self) -> int:
         return 2 if self.config.scheme == ICEBERG else 1
+
+    @property
+    def nimages(self) -> int:
+        """Exported images: the bucket levels, then (third level) pool and heads."""
+        return self.nlevels + (2 if self.config.pool_slabs else 0)
+
+    def level3_used(self) -> int:
+        """Slabs taken from the third level's pool so far."""
+        v = _U32(0)
+        _check(lib().cpht_level3_used(self._h, ctypes.byref(v)), "cpht_level3_used")
+        return v.value
 
     def _keys(self, keys: torch.Tensor) -> int:
         if keys.dtype != self.key_dtype:

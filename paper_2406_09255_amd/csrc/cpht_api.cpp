@@ -161,6 +161,32 @@ cpht_status_t configure_table(cpht_table* t, const cpht_config_t& c) {
       if (ok) t->cfg.subtile = (uint32_t)t->ice->G;
     }
   }
+  t->nimages = t->nlevels;
+  if (ok && c.pool_slabs > 0) {
+    // third iceberg level: lists addressed by the high log2_lists bits of
+    // pi_0(k); slots of 32 bits (64 with 64-bit primary slots)
+    const uint32_t S3 = c.slot_bits0 == 64 ? 64 : 32;
+    const uint32_t nb = c.log2_lists;
+    const uint32_t pbits = c.compact ? c.key_bits - (nb <= c.key_bits ? nb : 0) : c.key_bits;
+    ok = c.scheme == CPHT_ICEBERG && t->ice->l3 && nb <= c.key_bits && nb <= 30 && pbits + 1 <= S3 &&
+         c.pool_slabs < 0x7FFFFFFFu;  // slab ids stay below the busy-link marker
+    if (ok) {
+      Level3K& L3 = K.l3;
+      L3.L.nb = nb;
+      L3.L.pbits = pbits;
+      L3.L.pmask = mask_bits(pbits);
+      L3.L.bucket_words = 32;
+      L3.L.tbits = 0;
+      L3.nslabs = c.pool_slabs;
+      t->nimages = 4;
+      t->level_words[2] = (uint64_t)c.pool_slabs * 32;
+      t->level_words[3] = 1ull << nb;
+      t->slot_bits[2] = S3;
+      t->slot_bits[3] = 32;
+    }
+  } else {
+    t->cfg.log2_lists = 0;
+  }
   if (!ok) return CPHT_E_UNSUPPORTED;
   derive_perms(t, c.seed);
   return CPHT_OK;
@@ -236,16 +262,24 @@ cpht_status_t cpht_create(const cpht_config_t* cfg, cpht_table_t* out) {
     return CPHT_E_DEVICE;
   }
   hipError_t e = hipSuccess;
-  for (int x = 0; x < t->nlevels && e == hipSuccess; ++x) {
+  for (int x = 0; x < t->nimages && e == hipSuccess; ++x) {
     e = hipMalloc(reinterpret_cast<void**>(&t->level[x]), t->level_words[x] * 4);
     if (e == hipSuccess) e = hipMemset(t->level[x], 0, t->level_words[x] * 4);
-    K.lv[x].base = t->level[x];
+    if (x < t->nlevels) K.lv[x].base = t->level[x];
+  }
+  if (e == hipSuccess && t->nimages == 4) {
+    e = hipMalloc(reinterpret_cast<void**>(&t->l3_used), sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(t->l3_used, 0, sizeof(uint32_t));
+    K.l3.L.base = t->level[2];
+    K.l3.heads = t->level[3];
+    K.l3.used = t->l3_used;
   }
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&t->d_counter), sizeof(unsigned long long));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < 4; ++x)
       if (t->level[x]) (void)hipFree(t->level[x]);
+    if (t->l3_used) (void)hipFree(t->l3_used);
     if (t->d_counter) (void)hipFree(t->d_counter);
     delete t;
     return device_status(e);
@@ -258,8 +292,9 @@ cpht_status_t cpht_destroy(cpht_table_t t) {
   if (!t) return CPHT_E_ARG;
   if (!t->owns_memory) return CPHT_E_STATE;  // a view into a table set
   DeviceGuard g(t->device);
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < 4; ++x)
     if (t->level[x]) (void)hipFree(t->level[x]);
+  if (t->l3_used) (void)hipFree(t->l3_used);
   if (t->d_counter) (void)hipFree(t->d_counter);
   delete t;
   return CPHT_OK;
@@ -276,8 +311,12 @@ cpht_status_t cpht_clear(cpht_table_t t, uint64_t seed, void* stream) {
   DeviceGuard g(t->device);
   if (!g.ok) return CPHT_E_DEVICE;
   derive_perms(t, seed);
-  for (int x = 0; x < t->nlevels; ++x) {
+  for (int x = 0; x < t->nimages; ++x) {
     hipError_t e = launch_zero(t->level[x], t->level_words[x], as_stream(stream));
+    if (e != hipSuccess) return device_status(e);
+  }
+  if (t->l3_used) {
+    hipError_t e = launch_zero(t->l3_used, 1, as_stream(stream));
     if (e != hipSuccess) return device_status(e);
   }
   return CPHT_OK;
@@ -290,7 +329,7 @@ cpht_status_t cpht_insert(cpht_table_t t, const void* d_keys, uint64_t n, uint8_
   DeviceGuard g(t->device);
   if (!g.ok) return CPHT_E_DEVICE;
   const BatchK b = batch(d_keys, nullptr, d_out, n);
-  if (t->ice) t->ice->insert(t->tk, b, as_stream(stream));
+  if (t->ice) (t->nimages == 4 ? t->ice->insert3 : t->ice->insert)(t->tk, b, as_stream(stream));
   else t->ck->put(t->tk, b, as_stream(stream));
   return launched();
 }
@@ -306,7 +345,7 @@ cpht_status_t cpht_find(cpht_table_t t, const void* d_keys, uint64_t n, uint8_t*
   DeviceGuard g(t->device);
   if (!g.ok) return CPHT_E_DEVICE;
   const BatchK b = batch(d_keys, nullptr, d_found, n);
-  if (t->ice) t->ice->find(t->tk, b, as_stream(stream));
+  if (t->ice) (t->nimages == 4 ? t->ice->find3 : t->ice->find)(t->tk, b, as_stream(stream));
   else t->ck->find(t->tk, b, as_stream(stream));
   return launched();
 }
@@ -318,7 +357,7 @@ cpht_status_t cpht_delete(cpht_table_t t, const void* d_keys, uint64_t n, uint8_
   DeviceGuard g(t->device);
   if (!g.ok) return CPHT_E_DEVICE;
   const BatchK b = batch(d_keys, nullptr, d_out, n);
-  if (t->ice) t->ice->erase(t->tk, b, as_stream(stream));
+  if (t->ice) (t->nimages == 4 ? t->ice->erase3 : t->ice->erase)(t->tk, b, as_stream(stream));
   else t->ck->erase(t->tk, b, as_stream(stream));
   return launched();
 }
@@ -331,7 +370,7 @@ cpht_status_t cpht_mixed(cpht_table_t t, const void* d_keys, const uint8_t* d_op
   if (!d_keys || !d_ops || !d_out) return CPHT_E_ARG;
   DeviceGuard g(t->device);
   if (!g.ok) return CPHT_E_DEVICE;
-  t->ice->mixed(t->tk, batch(d_keys, d_ops, d_out, n), as_stream(stream));
+  (t->nimages == 4 ? t->ice->mixed3 : t->ice->mixed)(t->tk, batch(d_keys, d_ops, d_out, n), as_stream(stream));
   return launched();
 }
 
@@ -367,7 +406,7 @@ cpht_status_t cpht_count(cpht_table_t t, uint64_t* occupied, uint64_t* capacity,
   if (!g.ok) return CPHT_E_DEVICE;
   const hipStream_t s = as_stream(stream);
   hipError_t e = launch_zero_counter(t->d_counter, s);
-  for (int x = 0; x < t->nlevels && e == hipSuccess; ++x)
+  for (int x = 0; x < t->nimages && x < 3 && e == hipSuccess; ++x)  // bucket levels and the slab pool
     e = launch_count(t->level[x], t->level_words[x], (int)t->slot_bits[x], t->d_counter, s);
   unsigned long long h = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&h, t->d_counter, sizeof(h), hipMemcpyDeviceToHost, s);
@@ -383,19 +422,32 @@ cpht_status_t cpht_count(cpht_table_t t, uint64_t* occupied, uint64_t* capacity,
 }
 
 cpht_status_t cpht_level_bytes(cpht_table_t t, uint32_t level, uint64_t* bytes) {
-  if (!t || !bytes || level >= (uint32_t)t->nlevels) return CPHT_E_ARG;
+  if (!t || !bytes || level >= (uint32_t)t->nimages) return CPHT_E_ARG;
   *bytes = t->level_words[level] * 4;
   return CPHT_OK;
 }
 
 cpht_status_t cpht_level_ptr(cpht_table_t t, uint32_t level, void** d_ptr) {
-  if (!t || !d_ptr || level >= (uint32_t)t->nlevels) return CPHT_E_ARG;
+  if (!t || !d_ptr || level >= (uint32_t)t->nimages) return CPHT_E_ARG;
   *d_ptr = t->level[level];
   return CPHT_OK;
 }
 
+cpht_status_t cpht_level3_used(cpht_table_t t, uint32_t* slabs) {
+  if (!t || !slabs) return CPHT_E_ARG;
+  if (t->nimages != 4) return CPHT_E_STATE;
+  DeviceGuard g(t->device);
+  if (!g.ok) return CPHT_E_DEVICE;
+  uint32_t h = 0;
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(&h, t->l3_used, sizeof(h), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return device_status(e);
+  *slabs = h < t->cfg.pool_slabs ? h : t->cfg.pool_slabs;
+  return CPHT_OK;
+}
+
 cpht_status_t cpht_export(cpht_table_t t, uint32_t level, void* h_dst, uint64_t bytes) {
-  if (!t || !h_dst || level >= (uint32_t)t->nlevels || bytes != t->level_words[level] * 4) return CPHT_E_ARG;
+  if (!t || !h_dst || level >= (uint32_t)t->nimages || bytes != t->level_words[level] * 4) return CPHT_E_ARG;
   DeviceGuard g(t->device);
   if (!g.ok) return CPHT_E_DEVICE;
   hipError_t e = hipDeviceSynchronize();

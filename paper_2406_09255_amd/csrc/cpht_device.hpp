@@ -33,8 +33,22 @@ struct LevelK {
   uint32_t tbits;          // tag bits (cuckoo hash index, iceberg secondary index)
 };
 
+// Third iceberg level (Sec. 2.3: lists outside the table chosen by h_0(k)).
+// List a = the high nb bits of pi_0(k); each list is a chain of 128-byte
+// slabs from a fixed pool; a slab holds 32 / (S3 / 32) slots of S3 bits, the
+// last of which holds the id of the next slab (0 = end of the list).  Slab id
+// i (1-based) is pool words [(i - 1) * 32, i * 32).  nslabs = 0: no level 3.
+struct Level3K {
+  LevelK L;                // addressing and encoding (base = pool, bucket_words = 32)
+  uint32_t* heads;         // first slab id of each of the 2^L.nb lists
+  uint32_t* used;          // slabs handed out so far
+  uint32_t nslabs;         // pool capacity
+  uint32_t pad;
+};
+
 struct TableK {
   LevelK lv[2];
+  Level3K l3;
   PermK perm[3];
   uint64_t kmask;          // 2^w - 1
   uint32_t w;              // key bits

@@ -36,6 +36,35 @@ struct IceShape {
   static_assert(PER0 * G == B0 && PER1 * HG == B1, "slots per lane");
 };
 
+// Third level: a 128-byte slab read by the whole sub-tile, W3 words per
+// lane; slots of S3 = 32 bits (64 for 64-bit primary slots), the last slot of
+// a slab holding the next slab id.  Compiled only where every lane holds whole
+// slots (not for 64-bit slots with 32 lanes).
+template <int S0, int G>
+struct L3Shape {
+  static constexpr int S3 = S0 == 64 ? 64 : 32;
+  static constexpr int W3 = 32 / G;
+  static constexpr bool OK = W3 * 32 >= S3;
+  static constexpr int PER3 = OK ? W3 * 32 / S3 : 1;
+  static constexpr int B3 = 1024 / S3;
+  static constexpr int LINK = B3 - 1;             // slot index of the link
+  static constexpr int LINK_WORD = S3 == 32 ? 31 : 30;  // its word in the slab
+  static constexpr int LINK_LANE_WORD = OK ? LINK_WORD - (G - 1) * W3 : 0;  // in the last lane
+};
+
+// A list head or slab link being set: the value a key writes (by CAS from 0)
+// before it takes a slab from the pool and publishes the slab's id there.
+// Never a slab id (the pool has fewer than 2^31 - 1 slabs) and, with its top
+// bit clear, never a stored form.
+constexpr uint32_t LINK_BUSY = 0x7FFFFFFFu;
+
+// A fresh slab id from the pool, or 0 when the pool is used up.
+__device__ __forceinline__ uint32_t alloc_slab(const Level3K& L3) {
+  if (__hip_atomic_load(L3.used, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= L3.nslabs) return 0u;
+  const uint32_t id = __hip_atomic_fetch_add(L3.used, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+  return id <= L3.nslabs ? id : 0u;
+}
+
 // Keys whose buckets one sub-tile loads together (buffers within 32
 // registers per lane).
 template <int G, int W>
@@ -59,7 +88,9 @@ struct IceDepth {
 // by the tombstone with CAS (answer 1 if this operation did it, else 0).
 // Tombstones count as occupied everywhere and are never claimed, so the
 // order property and the lookup's early exit hold with deletes.
-template <class KeyT, int S0, int S1, int B0, int B1, int G, int MODE>
+// L3ON compiles the third level in (tables with a slab pool); without it the
+// two-level kernels carry none of its registers.
+template <class KeyT, int S0, int S1, int B0, int B1, int G, int MODE, bool L3ON>
 __device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, uint64_t idx) {
   constexpr bool WRITES = MODE == MODE_INSERT || MODE == MODE_MIXED;  // find-or-put claims
   using U = KeyT;
@@ -85,6 +116,16 @@ __device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, 
   const int half = st.rk >= HG ? 1 : 0;
   const int hr = st.rk & (HG - 1);
   const uint32_t hmask = HG == 32 ? 0xFFFFFFFFu : ((1u << HG) - 1u);
+  // level 3 (stage 3): the key's list and stored form, the slab being read
+  // (0 = list head not read yet), and slab slots known to be occupied (the
+  // link slot always)
+  using L3 = L3Shape<S0, G>;
+  constexpr int S3 = L3::S3, W3 = L3::W3, PER3 = L3::PER3;
+  constexpr uint32_t LINKBIT = 1u << L3::LINK;
+  constexpr bool L3C = L3ON && L3::OK;  // level-3 code compiled in
+  const bool l3on = L3C && T.l3.nslabs != 0u;
+  Split<U, S3> s3{0, 0};
+  uint32_t cur = 0, known3 = 0;
 
 #pragma unroll 1
   while (__ballot(stage != 0u) != 0ull) {
@@ -212,7 +253,13 @@ __device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, 
             continue;
           }
           if (!ins_t) {
-            if (mine) { result = 0; stage = 0; }
+            // k can only be on level 3 if both secondary buckets are full
+            bool to3 = false;
+            if (l3on) to3 = st.ballot(lane_first_empty<S1, W1>(buf[d], 0u) < PER1) == 0u;
+            if (mine) {
+              if (to3) { stage = 3; s3 = split_key<U, S3>(T, T.l3.L, 0, k, 0u); cur = 0; known3 = LINKBIT; }
+              else { result = 0; stage = 0; }
+            }
             continue;
           }
           KM1 knd = 0;
@@ -226,8 +273,11 @@ __device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, 
           if (em2) { f2 = HG + ctz32(em2); l2 = (uint32_t)((f2 - HG) * PER1) + st.bcast((uint32_t)le, f2); }
           const bool p1 = l1 < l2;  // bucket 1 only if strictly less full (ties go to bucket 2)
           const uint32_t lp = p1 ? l1 : l2;
-          if (lp == (uint32_t)B1) {
-            if (mine) { result = R_FULL; stage = 0; }
+          if (lp == (uint32_t)B1) {  // both secondary buckets full
+            if (mine) {
+              if (l3on) { stage = 3; s3 = split_key<U, S3>(T, T.l3.L, 0, k, 0u); cur = 0; known3 = LINKBIT; }
+              else { result = R_FULL; stage = 0; }
+            }
             continue;
           }
           uint32_t wf = 0;
@@ -254,14 +304,116 @@ __device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, 
         }
       }
     }
+    // ------------------------------------------------------------ level 3
+    // The list of k, slab by slab in list order: k's stored form before the
+    // first empty slot -> FOUND (lookup 1); else an insert claims the first
+    // empty slot (a lookup answers 0); a full slab is followed through its
+    // link.  An insert at an empty list or a full last slab sets the link:
+    // CAS 0 -> LINK_BUSY, and only the key that wins takes a slab from the
+    // pool and publishes its id (or 0 again, and FULL, when the pool is used
+    // up); a key that finds the link busy keeps its place and retries the CAS
+    // next superstep (a CAS result is never stale), so no slab is taken
+    // twice and every list is a chain set once per link, filling in one
+    // order as a bucket does.  A lookup treats a busy or empty link as the
+    // end of the list.
+    if constexpr (L3C) {
+      if (__ballot(stage == 3u) != 0ull) {
+        bool link = false, claim = false, erase = false;
+        uint32_t q = 0;
+        if (stage == 3u && cur == 0u) {  // read the list head
+          const uint32_t h = T.l3.heads[s3.a];
+          if (h != 0u && h != LINK_BUSY) cur = h;
+          else if (ins) link = true;
+          else { result = 0; stage = 0; }
+        }
+        constexpr int D3 = IceDepth<G, W3>::D;
+#pragma unroll 1
+        for (int t0 = 0; t0 < G; t0 += D3) {
+          uint32_t buf[D3][W3];
+          uint64_t ev[D3];
+          uint32_t kn[D3];
+          bool live[D3];
+#pragma unroll
+          for (int d = 0; d < D3; ++d) {
+            live[d] = st.bcast_bool(stage == 3u && cur != 0u && !link, t0 + d);
+            const uint32_t id = st.bcast(cur, t0 + d);
+            ev[d] = st.template bcast_slot<S3>(s3.e, t0 + d);
+            kn[d] = st.bcast(known3, t0 + d);
+            if (live[d]) load_words<W3>(buf[d], T.l3.L.base + (uint64_t)(id - 1u) * 32u + (uint32_t)(st.rk * W3));
+          }
+#pragma unroll
+          for (int d = 0; d < D3; ++d) {
+            if (!live[d]) continue;
+            const bool mine = st.rk == t0 + d;
+            const bool ins_t = MODE == MODE_MIXED ? st.bcast_bool(ins, t0 + d) : MODE == MODE_INSERT;
+            const uint32_t hits = st.ballot(lane_has<S3, W3>(buf[d], ev[d]));
+            if (hits) {
+              if constexpr (MODE == MODE_ERASE) {
+                const int f = ctz32(hits);
+                const uint32_t i = st.bcast((uint32_t)lane_match<S3, W3>(buf[d], ev[d]), f);
+                if (mine) { erase = true; q = (uint32_t)(f * PER3) + i; stage = 0; }
+              } else {
+                if (mine) { result = ins_t ? R_FOUND : 1; stage = 0; }
+              }
+              continue;
+            }
+            const uint32_t knd = ins_t ? kn[d] : LINKBIT;
+            const int le = lane_first_empty<S3, W3>(buf[d], lane_bits<PER3>(knd, st.rk * PER3));
+            const uint32_t em = st.ballot(le < PER3);
+            if (em) {
+              if (!ins_t) {
+                if (mine) { result = 0; stage = 0; }
+                continue;
+              }
+              const int f = ctz32(em);
+              const uint32_t lef = st.bcast((uint32_t)le, f);
+              if (mine) { claim = true; q = (uint32_t)(f * PER3) + lef; }
+              continue;
+            }
+            // slab full: its link
+            const uint32_t nx = st.bcast(buf[d][L3::LINK_LANE_WORD], G - 1);
+            if (mine) {
+              if (nx != 0u && nx != LINK_BUSY) { cur = nx; known3 = LINKBIT; }
+              else if (ins_t) link = true;
+              else { result = 0; stage = 0; }
+            }
+          }
+        }
+        uint32_t* slab = T.l3.L.base + (uint64_t)(cur - 1u) * 32u;
+        if constexpr (MODE == MODE_ERASE) {
+          if (erase) result = erase_at<S3>(slab, q, 0u, s3.e) ? 1 : 0;
+        }
+        if constexpr (WRITES) {
+          if (claim) {
+            const int r = claim_at<S3>(slab, q, 0u, s3.e);
+            if (r == CLAIM_WON) { result = R_PUT; stage = 0; }
+            else if (r == CLAIM_SAME) { result = R_FOUND; stage = 0; }
+            else known3 |= 1u << q;
+          }
+          if (link) {  // a new slab at the list head or after the full last slab
+            uint32_t* at = cur ? slab + L3::LINK_WORD : T.l3.heads + s3.a;
+            const uint32_t old = cas32(at, 0u, LINK_BUSY);
+            if (old == 0u) {
+              const uint32_t sl = alloc_slab(T.l3);
+              xchg32(at, sl);  // publish the slab, or release the link when the pool is used up
+              if (sl == 0u) { result = R_FULL; stage = 0; }
+              else { cur = sl; known3 = LINKBIT; }
+            } else if (old != LINK_BUSY) {  // linked by another key meanwhile
+              cur = old;
+              known3 = LINKBIT;
+            }
+          }
+        }
+      }
+    }
   }
   if (act) Bt.out[idx] = result;
 }
 
 // One table: key i of the batch is handled by global thread i.
-template <class KeyT, int S0, int S1, int B0, int B1, int G, int MODE>
+template <class KeyT, int S0, int S1, int B0, int B1, int G, int MODE, bool L3ON>
 __global__ __launch_bounds__(256) void iceberg_kernel(TableK T, BatchK Bt) {
-  iceberg_body<KeyT, S0, S1, B0, B1, G, MODE>(T, Bt, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  iceberg_body<KeyT, S0, S1, B0, B1, G, MODE, L3ON>(T, Bt, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // Many tables in one persistent launch: a fixed grid of blocks walks the
@@ -279,7 +431,7 @@ __global__ __launch_bounds__(256) void iceberg_multi_kernel(MultiK M) {
     Bt.ops = nullptr;
     Bt.out = M.out + ch.start;
     Bt.n = ch.count;
-    iceberg_body<KeyT, S0, S1, B0, B1, G, MODE>(T, Bt, threadIdx.x);
+    iceberg_body<KeyT, S0, S1, B0, B1, G, MODE, false>(T, Bt, threadIdx.x);
   }
 }
 

@@ -9,14 +9,18 @@
 #include "cpht_registry.hpp"
 
 // One table: its resolved configuration, kernel view and device memory.
+// Images 0 and 1 are the bucket levels; with a third iceberg level, image 2
+// is its slab pool and image 3 its list heads (nimages = 4).
 struct cpht_table {
   cpht_config_t cfg;
   int device;
-  int nlevels;
+  int nlevels;   // bucket levels: 1 (cuckoo) or 2 (iceberg)
+  int nimages;   // device arrays exported by cpht_export
   bool owns_memory;
-  uint32_t* level[2];
-  uint64_t level_words[2];
-  uint32_t slot_bits[2];
+  uint32_t* level[4];
+  uint64_t level_words[4];
+  uint32_t slot_bits[4];
+  uint32_t* l3_used;  // level 3: slabs handed out (device)
   unsigned long long* d_counter;
   cpht::TableK tk;
   const cpht::IceVariant* ice;

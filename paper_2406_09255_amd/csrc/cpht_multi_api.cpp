@@ -115,6 +115,10 @@ cpht_status_t cpht_multi_create(uint32_t n_tables, const cpht_config_t* cfgs, ui
   }
   // configure every table; all must share the scheme and the key word size
   for (uint32_t i = 0; i < n_tables; ++i) {
+    if (cfgs[i].pool_slabs != 0) {  // no third level inside a table set
+      free_multi(m);
+      return CPHT_E_UNSUPPORTED;
+    }
     const cpht_status_t st = configure_table(&m->tables[i], cfgs[i]);
     if (st != CPHT_OK || cfgs[i].scheme != cfgs[0].scheme ||
         (cfgs[i].key_bits > 32) != (cfgs[0].key_bits > 32)) {

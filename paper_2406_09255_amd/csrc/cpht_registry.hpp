@@ -13,7 +13,9 @@ struct IceVariant {
   int key64;           // 1: 64-bit key words
   int S0, S1, B0, B1;  // slot bits and bucket slots per level
   int G;               // sub-tile lanes
+  int l3;              // 1: a third level is possible (whole slots per lane on a slab)
   launch_fn find, insert, mixed, erase;
+  launch_fn find3, insert3, mixed3, erase3;  // with the third level compiled in (null if l3 = 0)
   multi_fn multi_find, multi_insert;
 };
 
