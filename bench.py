@@ -276,12 +276,13 @@ def level3(torch, cpht, synth, dev, reps=3):
     """Third iceberg level: compact 2^27 + 2^24 slots (16/32-bit), 37-bit keys,
     filled in one batch to load 1.0 of the bucket levels -- past the point
     where two levels answer FULL -- with and without a pool of 2^20 slabs
-    (128 MiB, 2^12 lists); then 2^26 finds (50 % hit).  Reports FULL answers,
+    (128 MiB) in 2^17 lists (one list per 32 primary buckets, so a list
+    holds about one slab of overflow); then 2^26 finds (50 % hit).  Reports FULL answers,
     keys that went to the lists, and insert / find rates."""
     w, L = 37, 27
     res = {"config": "iceberg 2^27 + 2^24 slots (16/32-bit), 37-bit keys, one insert batch to load 1.0 of the "
-                     "bucket levels, then 2^26 finds 50% hit; third level: 2^12 lists, pool of 2^20 slabs"}
-    for name, extra in (("two_levels", {}), ("three_levels", dict(log2_lists=12, pool_slabs=1 << 20))):
+                     "bucket levels, then 2^26 finds 50% hit; third level: 2^17 lists, pool of 2^20 slabs"}
+    for name, extra in (("two_levels", {}), ("three_levels", dict(log2_lists=17, pool_slabs=1 << 20))):
         t = cpht.Table(scheme=cpht.ICEBERG, key_bits=w, log2_slots0=L, log2_slots1=L - 3, bucket0=32, bucket1=16,
                        slot_bits0=16, slot_bits1=32, seed=11, **extra)
         cap = t.count()[1]
