@@ -76,6 +76,8 @@ typedef struct {
     uint32_t compact;      /* 1 = store remainders (quotienting); 0 = store the full pi_i(k) */
     uint32_t log2_lists;   /* iceberg third level: 2^log2_lists lists (ignored if pool_slabs = 0) */
     uint32_t pool_slabs;   /* iceberg third level: 128-byte slabs in its pool; 0 = two levels only */
+    uint32_t value_bytes;  /* iceberg map: 4 or 8 bytes of value per key; 0 = a set */
+    uint32_t pad;          /* must be 0 */
     uint64_t seed;         /* seed of the permutations pi_0, pi_1, pi_2 */
 } cpht_config_t;
 
@@ -106,6 +108,15 @@ cpht_status_t cpht_config_check(const cpht_config_t* cfg, cpht_config_t* resolve
  * the pool is used up.  Lookups and deletes walk the list when both
  * secondary buckets are full.  Not supported for 64-bit primary slots with
  * a 32-lane sub-tile, nor in table sets (CPHT_E_UNSUPPORTED). */
+
+/* Map (value_bytes = 4 or 8; iceberg only): the iceberg table is stable, a
+ * key never moves once stored, so its value sits at the same index as its
+ * slot in a parallel array per level (Sec. 2.1: a stable table can keep
+ * values in a separate array at the key's index; Sec. 6 notes maps as the
+ * case where compactness matters more).  Levels 0 and 1 get arrays of
+ * 2^log2_slots_x values, the third level pool_slabs * (slots per slab).
+ * Only cpht_insert_values writes values and cpht_find_values reads them; the
+ * set calls ignore them.  Not supported in table sets. */
 
 /* Create an empty table (synchronous: allocates and zeroes device memory).
  * Level x holds 2^log2_slots_x slots in buckets of bucket_x slots; each
@@ -169,6 +180,28 @@ cpht_status_t cpht_delete(cpht_table_t t, const void* d_keys, uint64_t n, uint8_
  * operation of the same batch inserts may answer either way. */
 cpht_status_t cpht_mixed(cpht_table_t t, const void* d_keys, const uint8_t* d_ops, uint64_t n, uint8_t* d_out,
                          void* stream);
+
+/* Map find-or-put (put if absent): like cpht_insert on an iceberg table, and
+ * the operation that stores keys[i] (answer CPHT_PUT) writes d_values[i] (4
+ * or 8 bytes each, as value_bytes) as its value; keys already present keep
+ * their value (CPHT_FOUND), so with repeats in one batch the stored value is
+ * that of the occurrence answered CPHT_PUT.  A concurrent lookup that finds
+ * a key stored by this call may read its value before it is written: values
+ * are complete for calls that follow in stream order.  CPHT_E_STATE without
+ * values. */
+cpht_status_t cpht_insert_values(cpht_table_t t, const void* d_keys, const void* d_values, uint64_t n,
+                                 uint8_t* d_out, void* stream);
+
+/* Map lookup: d_found[i] = 1 and d_values_out[i] = the value of keys[i] if it
+ * is stored, d_found[i] = 0 and d_values_out[i] unchanged otherwise. */
+cpht_status_t cpht_find_values(cpht_table_t t, const void* d_keys, uint64_t n, uint8_t* d_found,
+                               void* d_values_out, void* stream);
+
+/* Size of, and copy to host memory (synchronous) of, the value array of
+ * level 0, 1 or 2 (the third level's pool): value_bytes per slot, at the
+ * slot's index in cpht_export's image of that level. */
+cpht_status_t cpht_values_bytes(cpht_table_t t, uint32_t level, uint64_t* bytes);
+cpht_status_t cpht_export_values(cpht_table_t t, uint32_t level, void* h_dst, uint64_t bytes);
 
 /* Cuckoo only: find-or-put by sorting the batch, the baseline of the paper's
  * find-or-put experiment (Sec. 5, find-or-put benchmark): the keys are

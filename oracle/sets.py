@@ -41,6 +41,28 @@ def insert(S: np.ndarray, keys):
     return out, np.union1d(S, k)
 
 
+def insert_values(M: dict, keys, values):
+    """Map find-or-put applied in index order to the dictionary M (key ->
+    value): a key not in M is stored with the value of this operation (PUT),
+    a key already in M keeps its value (FOUND).  Returns the answers; M is
+    updated in place."""
+    out = np.empty(len(keys), np.uint8)
+    for i, (k, v) in enumerate(zip((int(x) for x in keys), (int(x) for x in values))):
+        if k in M:
+            out[i] = FOUND
+        else:
+            M[k] = v
+            out[i] = PUT
+    return out
+
+
+def find_values(M: dict, keys):
+    """Map lookup: (found, value) per key; value 0 where not found."""
+    found = np.array([int(k) in M for k in keys], dtype=np.uint8)
+    vals = np.array([M.get(int(k), 0) for k in keys], dtype=np.uint64)
+    return found, vals
+
+
 def delete(S: np.ndarray, keys):
     """Deletions applied in index order to S.
 

@@ -50,6 +50,8 @@ class Config(ctypes.Structure):
         ("compact", ctypes.c_uint32),
         ("log2_lists", ctypes.c_uint32),
         ("pool_slabs", ctypes.c_uint32),
+        ("value_bytes", ctypes.c_uint32),
+        ("pad", ctypes.c_uint32),
         ("seed", ctypes.c_uint64),
     ]
 
@@ -73,6 +75,10 @@ _SIGNATURES = {
     "cpht_find": (_I32, [_VP, _VP, _U64, _VP, _VP]),
     "cpht_mixed": (_I32, [_VP, _VP, _VP, _U64, _VP, _VP]),
     "cpht_delete": (_I32, [_VP, _VP, _U64, _VP, _VP]),
+    "cpht_insert_values": (_I32, [_VP, _VP, _VP, _U64, _VP, _VP]),
+    "cpht_find_values": (_I32, [_VP, _VP, _U64, _VP, _VP, _VP]),
+    "cpht_values_bytes": (_I32, [_VP, _U32, ctypes.POINTER(_U64)]),
+    "cpht_export_values": (_I32, [_VP, _U32, _VP, _U64]),
     "cpht_sorted_fop": (_I32, [_VP, _VP, _U64, _VP, _VP, _U64, _VP]),
     "cpht_sorted_fop_workspace": (_I32, [_VP, _U64, ctypes.POINTER(_U64)]),
     "cpht_count": (_I32, [_VP, ctypes.POINTER(_U64), ctypes.POINTER(_U64), _VP]),
@@ -294,6 +300,44 @@ class Table:
         _check(lib().cpht_delete(self._h, self._keys(keys), n, _dev_ptr(out, "out"), _stream(stream)),
                "cpht_delete")
         return out
+
+    def _values(self, values: torch.Tensor, n: int) -> int:
+        vb = self.config.value_bytes
+        want = torch.int64 if vb == 8 else torch.int32
+        if values.dtype != want or values.numel() < n:
+            raise ValueError(f"values must be a {want} device tensor with one value per key (value_bytes={vb})")
+        return _dev_ptr(values, "values")
+
+    def insert_values(self, keys: torch.Tensor, values: torch.Tensor, out: torch.Tensor | None = None,
+                      stream=None) -> torch.Tensor:
+        """Map find-or-put: the insert that stores keys[i] writes values[i]."""
+        n = keys.numel()
+        out = self._out(out, n, keys)
+        _check(lib().cpht_insert_values(self._h, self._keys(keys), self._values(values, n), n,
+                                        _dev_ptr(out, "out"), _stream(stream)), "cpht_insert_values")
+        return out
+
+    def find_values(self, keys: torch.Tensor, found: torch.Tensor | None = None, values: torch.Tensor | None = None,
+                    stream=None):
+        """Map lookup: (found, values); values of keys not found are left as given (zero when allocated here)."""
+        n = keys.numel()
+        found = self._out(found, n, keys)
+        if values is None:
+            values = torch.zeros(n, dtype=torch.int64 if self.config.value_bytes == 8 else torch.int32,
+                                 device=keys.device)
+        _check(lib().cpht_find_values(self._h, self._keys(keys), n, _dev_ptr(found, "found"),
+                                      self._values(values, n), _stream(stream)), "cpht_find_values")
+        return found, values
+
+    def export_values(self, level: int):
+        """Value array of level 0, 1 or 2 (third-level pool) in host memory (numpy uint8)."""
+        import numpy as np  # host staging buffer only
+
+        b = _U64(0)
+        _check(lib().cpht_values_bytes(self._h, level, ctypes.byref(b)), "cpht_values_bytes")
+        buf = np.empty(b.value, dtype=np.uint8)
+        _check(lib().cpht_export_values(self._h, level, buf.ctypes.data_as(_VP), b.value), "cpht_export_values")
+        return buf
 
     def sorted_fop_workspace(self, n: int) -> int:
         b = _U64(0)

@@ -187,6 +187,16 @@ cpht_status_t configure_table(cpht_table* t, const cpht_config_t& c) {
   } else {
     t->cfg.log2_lists = 0;
   }
+  if (ok && c.value_bytes != 0) {  // map values: stable iceberg table only
+    ok = c.scheme == CPHT_ICEBERG && (c.value_bytes == 4 || c.value_bytes == 8);
+    if (ok) {
+      K.vbytes = c.value_bytes;
+      t->val_bytes[0] = (1ull << c.log2_slots0) * c.value_bytes;
+      t->val_bytes[1] = (1ull << c.log2_slots1) * c.value_bytes;
+      if (t->nimages == 4) t->val_bytes[2] = t->level_words[2] * 32 / t->slot_bits[2] * c.value_bytes;
+    }
+  }
+  if (c.pad != 0) ok = false;
   if (!ok) return CPHT_E_UNSUPPORTED;
   derive_perms(t, c.seed);
   return CPHT_OK;
@@ -204,6 +214,8 @@ BatchK batch(const void* keys, const uint8_t* ops, uint8_t* out, uint64_t n) {
   b.ops = ops;
   b.out = out;
   b.n = n;
+  b.vin = nullptr;
+  b.vout = nullptr;
   return b;
 }
 
@@ -274,11 +286,19 @@ cpht_status_t cpht_create(const cpht_config_t* cfg, cpht_table_t* out) {
     K.l3.heads = t->level[3];
     K.l3.used = t->l3_used;
   }
+  for (int x = 0; x < 3 && e == hipSuccess; ++x) {
+    if (!t->val_bytes[x]) continue;
+    e = hipMalloc(reinterpret_cast<void**>(&t->vals[x]), t->val_bytes[x]);
+    if (e == hipSuccess) e = hipMemset(t->vals[x], 0, t->val_bytes[x]);
+    K.vals[x] = t->vals[x];
+  }
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&t->d_counter), sizeof(unsigned long long));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     for (int x = 0; x < 4; ++x)
       if (t->level[x]) (void)hipFree(t->level[x]);
+    for (int x = 0; x < 3; ++x)
+      if (t->vals[x]) (void)hipFree(t->vals[x]);
     if (t->l3_used) (void)hipFree(t->l3_used);
     if (t->d_counter) (void)hipFree(t->d_counter);
     delete t;
@@ -294,6 +314,8 @@ cpht_status_t cpht_destroy(cpht_table_t t) {
   DeviceGuard g(t->device);
   for (int x = 0; x < 4; ++x)
     if (t->level[x]) (void)hipFree(t->level[x]);
+  for (int x = 0; x < 3; ++x)
+    if (t->vals[x]) (void)hipFree(t->vals[x]);
   if (t->l3_used) (void)hipFree(t->l3_used);
   if (t->d_counter) (void)hipFree(t->d_counter);
   delete t;
@@ -317,6 +339,11 @@ cpht_status_t cpht_clear(cpht_table_t t, uint64_t seed, void* stream) {
   }
   if (t->l3_used) {
     hipError_t e = launch_zero(t->l3_used, 1, as_stream(stream));
+    if (e != hipSuccess) return device_status(e);
+  }
+  for (int x = 0; x < 3; ++x) {
+    if (!t->vals[x]) continue;
+    hipError_t e = launch_zero(reinterpret_cast<uint32_t*>(t->vals[x]), t->val_bytes[x] / 4, as_stream(stream));
     if (e != hipSuccess) return device_status(e);
   }
   return CPHT_OK;
@@ -372,6 +399,52 @@ cpht_status_t cpht_mixed(cpht_table_t t, const void* d_keys, const uint8_t* d_op
   if (!g.ok) return CPHT_E_DEVICE;
   (t->nimages == 4 ? t->ice->mixed3 : t->ice->mixed)(t->tk, batch(d_keys, d_ops, d_out, n), as_stream(stream));
   return launched();
+}
+
+cpht_status_t cpht_insert_values(cpht_table_t t, const void* d_keys, const void* d_values, uint64_t n,
+                                 uint8_t* d_out, void* stream) {
+  if (!t) return CPHT_E_ARG;
+  if (!t->tk.vbytes) return CPHT_E_STATE;
+  if (n == 0) return CPHT_OK;
+  if (!d_keys || !d_values || !d_out) return CPHT_E_ARG;
+  DeviceGuard g(t->device);
+  if (!g.ok) return CPHT_E_DEVICE;
+  BatchK b = batch(d_keys, nullptr, d_out, n);
+  b.vin = d_values;
+  (t->nimages == 4 ? t->ice->insert_v3 : t->ice->insert_v)(t->tk, b, as_stream(stream));
+  return launched();
+}
+
+cpht_status_t cpht_find_values(cpht_table_t t, const void* d_keys, uint64_t n, uint8_t* d_found,
+                               void* d_values_out, void* stream) {
+  if (!t) return CPHT_E_ARG;
+  if (!t->tk.vbytes) return CPHT_E_STATE;
+  if (n == 0) return CPHT_OK;
+  if (!d_keys || !d_found || !d_values_out) return CPHT_E_ARG;
+  DeviceGuard g(t->device);
+  if (!g.ok) return CPHT_E_DEVICE;
+  BatchK b = batch(d_keys, nullptr, d_found, n);
+  b.vout = d_values_out;
+  (t->nimages == 4 ? t->ice->find_v3 : t->ice->find_v)(t->tk, b, as_stream(stream));
+  return launched();
+}
+
+cpht_status_t cpht_values_bytes(cpht_table_t t, uint32_t level, uint64_t* bytes) {
+  if (!t || !bytes || level > 2) return CPHT_E_ARG;
+  if (!t->vals[level]) return CPHT_E_STATE;
+  *bytes = t->val_bytes[level];
+  return CPHT_OK;
+}
+
+cpht_status_t cpht_export_values(cpht_table_t t, uint32_t level, void* h_dst, uint64_t bytes) {
+  if (!t || !h_dst || level > 2) return CPHT_E_ARG;
+  if (!t->vals[level]) return CPHT_E_STATE;
+  if (bytes != t->val_bytes[level]) return CPHT_E_ARG;
+  DeviceGuard g(t->device);
+  if (!g.ok) return CPHT_E_DEVICE;
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(h_dst, t->vals[level], bytes, hipMemcpyDeviceToHost);
+  return device_status(e);
 }
 
 cpht_status_t cpht_sorted_fop_workspace(cpht_table_t t, uint64_t n, uint64_t* bytes) {

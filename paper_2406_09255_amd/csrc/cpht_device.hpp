@@ -56,7 +56,10 @@ struct TableK {
   uint32_t H;              // cuckoo hash functions
   uint32_t C;              // cuckoo chain bound
   uint32_t compact;        // 1: payload is the remainder
-  uint32_t pad;
+  uint32_t vbytes;         // map values: 0 (a set), 4 or 8 bytes per slot
+  // Map values (stable iceberg table: a key's value sits at its slot's index
+  // in a parallel array, Sec. 2.1): level 0, level 1, and the slab pool.
+  uint8_t* vals[3];
 };
 
 struct BatchK {
@@ -64,7 +67,27 @@ struct BatchK {
   const uint8_t* ops;      // mixed batches: 0 = find, 1 = insert
   uint8_t* out;            // one result byte per key
   uint64_t n;
+  const void* vin;         // map inserts: one value per key (vbytes each)
+  void* vout;              // map lookups: the value of each key found
 };
+
+// Value of slot `index` of a level: map insert writes it (put-if-absent:
+// only the operation that stored the key), map lookup reads it.
+__device__ __forceinline__ void put_value(const TableK& T, int level, uint64_t index, const BatchK& Bt,
+                                          uint64_t idx) {
+  if (T.vbytes == 8)
+    reinterpret_cast<uint64_t*>(T.vals[level])[index] = static_cast<const uint64_t*>(Bt.vin)[idx];
+  else
+    reinterpret_cast<uint32_t*>(T.vals[level])[index] = static_cast<const uint32_t*>(Bt.vin)[idx];
+}
+
+__device__ __forceinline__ void get_value(const TableK& T, int level, uint64_t index, const BatchK& Bt,
+                                          uint64_t idx) {
+  if (T.vbytes == 8)
+    static_cast<uint64_t*>(Bt.vout)[idx] = reinterpret_cast<const uint64_t*>(T.vals[level])[index];
+  else
+    static_cast<uint32_t*>(Bt.vout)[idx] = reinterpret_cast<const uint32_t*>(T.vals[level])[index];
+}
 
 // A launch over many tables: chunk b = keys [start, start + count) of the
 // concatenated key array, all of table `table` (count <= 256).

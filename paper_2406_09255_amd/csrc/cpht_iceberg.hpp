@@ -22,7 +22,7 @@
 
 namespace cpht {
 
-enum : int { MODE_FIND = 0, MODE_INSERT = 1, MODE_MIXED = 2, MODE_ERASE = 3 };
+enum : int { MODE_FIND = 0, MODE_INSERT = 1, MODE_MIXED = 2, MODE_ERASE = 3, MODE_FIND_V = 4, MODE_INSERT_V = 5 };
 
 template <int S0, int S1, int B0, int B1, int G>
 struct IceShape {
@@ -90,8 +90,14 @@ struct IceDepth {
 // order property and the lookup's early exit hold with deletes.
 // L3ON compiles the third level in (tables with a slab pool); without it the
 // two-level kernels carry none of its registers.
-template <class KeyT, int S0, int S1, int B0, int B1, int G, int MODE, bool L3ON>
+// MODE_FIND_V / MODE_INSERT_V are lookup / find-or-put of a map: the value of
+// a key sits at its slot's index in a parallel array (the table is stable);
+// the insert that stores a key writes its value, a lookup that finds the key
+// returns it.
+template <class KeyT, int S0, int S1, int B0, int B1, int G, int MODE_, bool L3ON>
 __device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, uint64_t idx) {
+  constexpr bool VALS = MODE_ == MODE_FIND_V || MODE_ == MODE_INSERT_V;
+  constexpr int MODE = MODE_ == MODE_FIND_V ? MODE_FIND : MODE_ == MODE_INSERT_V ? MODE_INSERT : MODE_;
   constexpr bool WRITES = MODE == MODE_INSERT || MODE == MODE_MIXED;  // find-or-put claims
   using U = KeyT;
   using Sh = IceShape<S0, S1, B0, B1, G>;
@@ -160,6 +166,14 @@ __device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, 
               uint32_t wf = 0;
               if constexpr (S0 == 16) wf = st.bcast(get_word<W0>(buf[d], (int)(i >> 1)), f);
               if (mine) { erase = true; q = (uint32_t)(f * PER0) + i; word = wf; stage = 0; }
+            } else if constexpr (VALS && MODE == MODE_FIND) {
+              const int f = ctz32(hits);
+              const uint32_t i = st.bcast((uint32_t)lane_match<S0, W0>(buf[d], ev[d]), f);
+              if (mine) {
+                result = 1;
+                stage = 0;
+                get_value(T, 0, s0.a * B0 + (uint64_t)(f * PER0) + i, Bt, idx);
+              }
             } else {
               if (mine) { result = ins_t ? R_FOUND : 1; stage = 0; }
             }
@@ -187,7 +201,11 @@ __device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, 
       if constexpr (WRITES) {
         if (claim) {
           const int r = claim_at<S0>(L0.base + s0.a * L0.bucket_words, q, word, s0.e);
-          if (r == CLAIM_WON) { result = R_PUT; stage = 0; }
+          if (r == CLAIM_WON) {
+            result = R_PUT;
+            stage = 0;
+            if constexpr (VALS) put_value(T, 0, s0.a * B0 + q, Bt, idx);
+          }
           else if (r == CLAIM_SAME) { result = R_FOUND; stage = 0; }
           else known0 |= (KM0)1 << q;
         }
@@ -247,6 +265,15 @@ __device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, 
                 word = wf;
                 stage = 0;
               }
+            } else if constexpr (VALS && MODE == MODE_FIND) {
+              const int f = ctz32(hits);
+              const uint32_t i = st.bcast((uint32_t)lane_match<S1, W1>(buf[d], ev[d]), f);
+              if (mine) {
+                result = 1;
+                stage = 0;
+                const uint64_t ab = f >= HG ? s2.a : s1.a;
+                get_value(T, 1, ab * B1 + (uint64_t)((f & (HG - 1)) * PER1) + i, Bt, idx);
+              }
             } else {
               if (mine) { result = ins_t ? R_FOUND : 1; stage = 0; }
             }
@@ -297,7 +324,11 @@ __device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, 
           const uint64_t ab = pick2 ? s2.a : s1.a;
           const uint64_t e = pick2 ? s2.e : s1.e;
           const int r = claim_at<S1>(L1.base + ab * L1.bucket_words, q, word, e);
-          if (r == CLAIM_WON) { result = R_PUT; stage = 0; }
+          if (r == CLAIM_WON) {
+            result = R_PUT;
+            stage = 0;
+            if constexpr (VALS) put_value(T, 1, ab * B1 + q, Bt, idx);
+          }
           else if (r == CLAIM_SAME) { result = R_FOUND; stage = 0; }
           else if (pick2) known2 |= (KM1)1 << q;
           else known1 |= (KM1)1 << q;
@@ -352,6 +383,14 @@ __device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, 
                 const int f = ctz32(hits);
                 const uint32_t i = st.bcast((uint32_t)lane_match<S3, W3>(buf[d], ev[d]), f);
                 if (mine) { erase = true; q = (uint32_t)(f * PER3) + i; stage = 0; }
+              } else if constexpr (VALS && MODE == MODE_FIND) {
+                const int f = ctz32(hits);
+                const uint32_t i = st.bcast((uint32_t)lane_match<S3, W3>(buf[d], ev[d]), f);
+                if (mine) {
+                  result = 1;
+                  stage = 0;
+                  get_value(T, 2, (uint64_t)(cur - 1u) * L3::B3 + (uint64_t)(f * PER3) + i, Bt, idx);
+                }
               } else {
                 if (mine) { result = ins_t ? R_FOUND : 1; stage = 0; }
               }
@@ -386,7 +425,11 @@ __device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, 
         if constexpr (WRITES) {
           if (claim) {
             const int r = claim_at<S3>(slab, q, 0u, s3.e);
-            if (r == CLAIM_WON) { result = R_PUT; stage = 0; }
+            if (r == CLAIM_WON) {
+              result = R_PUT;
+              stage = 0;
+              if constexpr (VALS) put_value(T, 2, (uint64_t)(cur - 1u) * L3::B3 + q, Bt, idx);
+            }
             else if (r == CLAIM_SAME) { result = R_FOUND; stage = 0; }
             else known3 |= 1u << q;
           }

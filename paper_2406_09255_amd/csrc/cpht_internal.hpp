@@ -21,6 +21,8 @@ struct cpht_table {
   uint64_t level_words[4];
   uint32_t slot_bits[4];
   uint32_t* l3_used;  // level 3: slabs handed out (device)
+  uint8_t* vals[3];   // map values of levels 0, 1 and the slab pool (device)
+  uint64_t val_bytes[3];
   unsigned long long* d_counter;
   cpht::TableK tk;
   const cpht::IceVariant* ice;

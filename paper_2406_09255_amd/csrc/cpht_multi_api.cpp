@@ -115,7 +115,7 @@ cpht_status_t cpht_multi_create(uint32_t n_tables, const cpht_config_t* cfgs, ui
   }
   // configure every table; all must share the scheme and the key word size
   for (uint32_t i = 0; i < n_tables; ++i) {
-    if (cfgs[i].pool_slabs != 0) {  // no third level inside a table set
+    if (cfgs[i].pool_slabs != 0 || cfgs[i].value_bytes != 0) {  // no third level or map values in a set
       free_multi(m);
       return CPHT_E_UNSUPPORTED;
     }

@@ -16,6 +16,7 @@ struct IceVariant {
   int l3;              // 1: a third level is possible (whole slots per lane on a slab)
   launch_fn find, insert, mixed, erase;
   launch_fn find3, insert3, mixed3, erase3;  // with the third level compiled in (null if l3 = 0)
+  launch_fn find_v, insert_v, find_v3, insert_v3;  // map lookup / find-or-put (values), without / with level 3
   multi_fn multi_find, multi_insert;
 };
 
@@ -48,6 +49,24 @@ struct CkVariant {
 
 const IceVariant* ice_variants_u32(int* n);
 const IceVariant* ice_variants_u64(int* n);
+
+// Iceberg launchers come from three translation units per key word (compiled
+// in parallel), one entry per CPHT_ICE_LIST position; cpht_registry.cpp
+// assembles them into IceVariant records.
+struct IceLaunch4 {
+  launch_fn a, b, c, d;
+};
+struct IceMulti2 {
+  multi_fn find, insert;
+};
+const IceLaunch4* ice_base_u32();   // find, insert, mixed, erase
+const IceMulti2* ice_multi_u32();   // table-set find, insert
+const IceLaunch4* ice_l3_u32();     // the same four with the third level (null where impossible)
+const IceLaunch4* ice_map_u32();    // map find, map insert, and both with the third level
+const IceLaunch4* ice_base_u64();
+const IceMulti2* ice_multi_u64();
+const IceLaunch4* ice_l3_u64();
+const IceLaunch4* ice_map_u64();
 const CkVariant* ck_variants_u32(int* n);
 const CkVariant* ck_variants_u64(int* n);
 

@@ -84,3 +84,29 @@ def test_sorted_fop_over_capacity_accounting():
     later = np.ones(keys.size, bool)
     later[first] = False
     assert not (out[later] == oracle.PUT).any()
+
+
+def test_map_definition_worked_example():
+    """Put-if-absent: the first value offered for a key stays."""
+    from oracle import sets
+    M: dict = {}
+    out = sets.insert_values(M, [5, 9, 5, 7, 9], [50, 90, 51, 70, 91])
+    assert out.tolist() == [oracle.PUT, oracle.PUT, oracle.FOUND, oracle.PUT, oracle.FOUND]
+    assert M == {5: 50, 9: 90, 7: 70}
+    found, vals = sets.find_values(M, [7, 8, 5])
+    assert found.tolist() == [1, 0, 1] and vals.tolist() == [70, 0, 50]
+
+
+def test_map_answers_equal_set_answers():
+    from oracle import sets
+    rng = np.random.default_rng(3)
+    keys = rng.integers(0, 200, size=500).astype(np.uint64)
+    vals = rng.integers(0, 1 << 40, size=500).astype(np.uint64)
+    M: dict = {}
+    out = sets.insert_values(M, keys, vals)
+    want, S = sets.insert(np.zeros(0, np.uint64), keys)
+    assert np.array_equal(out, want)
+    assert sorted(M) == S.tolist()
+    # each stored value is the one offered at the key's first occurrence
+    _, first = np.unique(keys, return_index=True)
+    assert all(M[int(keys[i])] == int(vals[i]) for i in first)
