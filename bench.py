@@ -116,8 +116,8 @@ class Runner:
 
 # Optional sections of the JSON line (each has a --no-<name> switch or is
 # picked with --only).
-SECTIONS = ("plain", "equal", "window", "sweep", "small", "iceberg", "fop", "delete", "level3", "many", "serving",
-            "ceilings", "cpu")
+SECTIONS = ("plain", "equal", "window", "sweep", "small", "iceberg", "fop", "delete", "level3", "map", "many",
+            "serving", "ceilings", "cpu")
 
 # (slot bits, compact, slots per bucket) of the load sweep: compact 32-bit and
 # plain 64-bit slots at 8, 16 and 32 slots per bucket.
@@ -316,6 +316,65 @@ def level3(torch, cpht, synth, dev, reps=3):
             row["pool_bytes"] = t.level_bytes(2)
         res[name] = row
         del t, keys, q, out, found
+    return res
+
+
+def kv_map(torch, cpht, synth, dev, reps=3):
+    """Key-value map on the iceberg table (values at the slot index of their
+    key, 8 bytes each): 2^27 + 2^24 slots, 37-bit keys, insert to load 0.9
+    in one batch then 2^26 lookups (50 % hit), compact 16/32-bit against
+    plain 64/64-bit slots, beside the same workload as a set."""
+    w, L = 37, 27
+    res = {"config": "iceberg 2^27 + 2^24 slots, 37-bit keys, 8-byte values; insert to load 0.9 then 2^26 lookups "
+                     "50% hit"}
+    shapes = (("map_16_32", dict(slot_bits0=16, slot_bits1=32, value_bytes=8)),
+              ("map_64_64", dict(slot_bits0=64, slot_bits1=64, compact=0, value_bytes=8)),
+              ("set_16_32", dict(slot_bits0=16, slot_bits1=32)))
+    for name, kw in shapes:
+        t = cpht.Table(scheme=cpht.ICEBERG, key_bits=w, log2_slots0=L, log2_slots1=L - 3, bucket0=32, bucket1=16,
+                       seed=12, **kw)
+        cap = t.count()[1]
+        n = int(0.9 * cap)
+        keys = synth.distinct_keys(w, KEY_SEED + 17, 0, n, device=dev)
+        vals = synth.mix64_t(keys)
+        q = synth.find_queries(w, KEY_SEED + 17, n, N_FIND, 0.5, Q_SEED + 17, device=dev)
+        out = torch.empty(n, dtype=torch.uint8, device=dev)
+        found = torch.empty(N_FIND, dtype=torch.uint8, device=dev)
+        vout = torch.zeros(N_FIND, dtype=torch.int64, device=dev)
+        ti, tf = [], []
+        for rep in range(reps + 1):
+            t.clear(80 + rep)
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record()
+            if "value_bytes" in kw:
+                t.insert_values(keys, vals, out)
+            else:
+                t.insert(keys, out)
+            e[1].record()
+            if "value_bytes" in kw:
+                t.find_values(q, found, vout)
+            else:
+                t.find(q, found)
+            e[2].record()
+            e[2].synchronize()
+            if rep:
+                ti.append(e[0].elapsed_time(e[1]))
+                tf.append(e[1].elapsed_time(e[2]))
+        ok = int((out == cpht.PUT).sum().item()) == n and abs(float(found.float().mean().item()) - 0.5) < 0.01
+        if "value_bytes" in kw:  # every value returned is the one inserted with its key
+            hit = found.bool()
+            ok = ok and torch.equal(vout[hit], synth.mix64_t(q[hit]))
+        bytes_ = sum(t.level_bytes(x) for x in range(2))
+        if "value_bytes" in kw:
+            bytes_ += cap * 8
+        res[name] = {"insert_mops": round(n / (sum(ti) / len(ti) / 1000.0) / 1e6, 1),
+                     "find_mops": round(N_FIND / (sum(tf) / len(tf) / 1000.0) / 1e6, 1),
+                     "bytes": bytes_, "check": "ok" if ok else "FAILED"}
+        del t, keys, vals, q, out, found, vout
+    res["compact_vs_plain_map"] = {
+        "insert": round(res["map_16_32"]["insert_mops"] / res["map_64_64"]["insert_mops"], 3),
+        "find": round(res["map_16_32"]["find_mops"] / res["map_64_64"]["find_mops"], 3),
+        "memory": round(res["map_16_32"]["bytes"] / res["map_64_64"]["bytes"], 3)}
     return res
 
 
@@ -980,6 +1039,9 @@ def main():
 
     if not args.no_level3:
         res["level3"] = level3(torch, cpht, synth, dev)
+
+    if not args.no_map:
+        res["map"] = kv_map(torch, cpht, synth, dev)
 
     if not args.no_many:
         res["many_tables"] = many_tables(torch, cpht, synth, dev)
