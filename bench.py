@@ -47,7 +47,7 @@ SECTOR = 64  # write-back unit of a modified slot (measured: 68.7 B written per 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by the
 # copy-kernel calibration factors 2.0 / 1.0), profiles/cuckoo_c2_hbm_bytes.md.
 # Valid only for the kernel sources they were taken with (hash of KERNEL_SOURCES below).
-TRAFFIC = {"csrc_sha": "c3ccc29ee78f954b", "cuckoo_put": 25743142708, "cuckoo_find": 11034975937}
+TRAFFIC = {"csrc_sha": "0d93f8ec9af4f898", "cuckoo_put": 25742989235, "cuckoo_find": 11034847358}
 
 
 # The sources the profiled cuckoo kernels are compiled from.
