@@ -680,38 +680,52 @@ def many_tables(torch, cpht, synth, dev, n_tables=4096, lo=10, hi=20, load=0.85,
     }
 
 
-def iceberg_zipf(torch, cpht, synth, dev, log2_slots0=28, batch=1 << 20, n_batches=200):
+def iceberg_zipf(torch, cpht, synth, dev, log2_slots0=28, batch=1 << 20, max_batches=8000, chunk=250,
+                 target=0.9):
     """Dynamic operation under skew: 2^28 + 2^25 slots, mixed batches of
     `batch` operations (half finds, half find-or-puts), keys Zipf(1.1) over
     2^34 ranks mapped to 34-bit keys by a bijection, for inserts and finds
     alike; the hottest key is about 10 % of all draws, so most inserts repeat
-    a key already present."""
+    a key already present.  Runs until the table reaches `target` load or an
+    insert answers FULL (at most max_batches batches).  Keys are generated on
+    the device in chunks between timed regions; each batch is timed alone."""
     w = 34
     L0, L1 = log2_slots0, log2_slots0 - 3
-    rows = {}
     t = cpht.Table(scheme=cpht.ICEBERG, key_bits=w, log2_slots0=L0, log2_slots1=L1, bucket0=32, bucket1=16,
                    slot_bits0=16, slot_bits1=32, seed=19)
+    cap = t.count()[1]
     ops = (synth.uniform_below(0x2F, batch, 2, dev)).to(torch.uint8)
-    out = torch.empty(batch, dtype=torch.uint8, device=dev)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(n_batches + 1)]
-    keys = [synth.zipf_keys(w, KEY_SEED + 5, 1.1, batch, 1000 + b, device=dev) for b in range(n_batches)]
-    torch.cuda.synchronize()
-    puts = torch.zeros((), dtype=torch.int64, device=dev)
-    ev[0].record()
-    for b in range(n_batches):
-        t.mixed(keys[b], ops, out)
-        ev[b + 1].record()
-        puts += (out == cpht.PUT).sum()
-    torch.cuda.synchronize()
-    lat = [ev[b].elapsed_time(ev[b + 1]) for b in range(n_batches)]
-    occ, cap = t.count()
-    ms = sum(lat)
-    rows = {"mops": round(n_batches * batch / ms / 1e3, 1),
+    outs = torch.empty((chunk, batch), dtype=torch.uint8, device=dev)
+    lat, curve = [], []
+    b, occ, first_full, puts = 0, 0, None, 0
+    while b < max_batches and occ < target * cap and first_full is None:
+        nb = min(chunk, max_batches - b)
+        keys = [synth.zipf_keys(w, KEY_SEED + 5, 1.1, batch, 1000 + b + i, device=dev) for i in range(nb)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(nb + 1)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        for i in range(nb):
+            t.mixed(keys[i], ops, outs[i])
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(nb)]
+        lat += ms
+        full_rows = torch.nonzero((outs[:nb] == cpht.FULL).any(dim=1))
+        if full_rows.numel():
+            first_full = b + int(full_rows[0].item())
+        puts += int(((outs[:nb] == cpht.PUT) & (ops == 1)).sum().item())  # finds answer 1 too
+        occ = t.count()[0]
+        b += nb
+        curve.append({"batches": b, "load": round(occ / cap, 4), "mops": round(nb * batch / sum(ms) / 1e3, 1)})
+        del keys
+    rows = {"mops": round(b * batch / sum(lat) / 1e3, 1),
             "batch_latency_ms": {"p50": round(pct(lat, 50), 4), "p99": round(pct(lat, 99), 4)},
-            "puts": int(puts.item()), "fill_factor": round(occ / cap, 4),
-            "config": (f"iceberg 2^{L0} + 2^{L1} slots (16/32-bit), {w}-bit keys Zipf(1.1) over 2^34 ranks; "
-                       f"{n_batches} mixed batches of {batch} ops (50% find / 50% find-or-put)")}
-    del t, keys
+            "batches": b, "operations": b * batch, "puts": puts, "fill_factor": round(occ / cap, 4),
+            "first_full_batch": first_full, "by_load": curve[:: max(1, len(curve) // 12)] + curve[-1:],
+            "config": (f"iceberg 2^{L0} + 2^{L1} slots (16/32-bit), {w}-bit keys Zipf(1.1) over 2^34 ranks; mixed "
+                       f"batches of {batch} ops (50% find / 50% find-or-put) until load {target} or the first "
+                       f"FULL (at most {max_batches} batches)")}
+    del t, outs
     return rows
 
 
