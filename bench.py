@@ -729,7 +729,7 @@ def iceberg_zipf(torch, cpht, synth, dev, log2_slots0=28, batch=1 << 20, max_bat
     return rows
 
 
-def serving(torch, cpht, synth, dev, n_req=4000, log2_slots0=32, prefill=0.5, seed=3):
+def serving(torch, cpht, synth, dev, n_req=20000, log2_slots0=32, prefill=0.5, seed=3):
     """Serving loop over one resident compact iceberg table of 2^32 + 2^29
     slots (16/32-bit, 40-bit keys), pre-filled to load 0.5.  Requests: sizes
     lognormal (median 4096, sigma 2) clipped to 1..2^22; 70 % finds (half hits)
