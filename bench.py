@@ -40,6 +40,11 @@ LINE = 128
 # cuckoo put rounds (one bucket read and one bucket write each) and find probes.
 ROUNDS_PER_PUT = {0.5: 1.00002, 0.7: 1.00252, 0.8: 1.01291, 0.9: 1.05175, 0.95: 1.11011}
 PROBES_PER_FIND = {0.5: 1.00014, 0.7: 1.01809, 0.8: 1.07518, 0.9: 1.22454, 0.95: 1.36303}
+# Iceberg at load 0.9 (B0 = 32, B1 = 16; sequential oracle at 2^22 primary
+# slots, 50 % hit finds): an insert reads its primary bucket and, with
+# probability ICE_L2["put"], both secondary buckets; a find likewise with
+# probability ICE_L2["find"] (put / find bucket reads 1.15165 / 1.62852).
+ICE_L2 = {"put": 0.075824, "find": 0.314262}
 KEY_BYTES = 8
 RESULT_BYTES = 1
 SECTOR = 64  # write-back unit of a modified slot (measured: 68.7 B written per put at 1.05 rounds)
@@ -493,10 +498,23 @@ def iceberg_static(torch, cpht, synth, dev, reps=3):
         occ, cap_ = t.count()
         nfull = int((out == cpht.FULL).sum().item())
         ti, tf = sum(ins) / len(ins), sum(fnd) / len(fnd)
+        # algorithmic bytes and random bucket reads (128-byte lines) per operation
+        b0, b1 = 32 * s0 // 8, 16 * s1 // 8
+        l0, l1 = -(-b0 // LINE), -(-b1 // LINE)
+        ins_b = b0 + 2 * ICE_L2["put"] * b1 + SECTOR + KEY_BYTES + RESULT_BYTES
+        fnd_b = b0 + 2 * ICE_L2["find"] * b1 + KEY_BYTES + RESULT_BYTES
+        ins_l, fnd_l = l0 + 2 * ICE_L2["put"] * l1, l0 + 2 * ICE_L2["find"] * l1
         rows[label] = {"insert_mops": round(n / ti / 1e3, 1), "find_mops": round(N_FIND / tf / 1e3, 1),
                        "insert_ms": round(ti, 3), "find_ms": round(tf, 3), "full": nfull,
                        "fill_factor": round(occ / cap_, 4),
-                       "table_bytes": t.level_bytes(0) + t.level_bytes(1)}
+                       "table_bytes": t.level_bytes(0) + t.level_bytes(1),
+                       "roofline": {
+                           "insert": {"bytes_per_op": round(ins_b, 1), "GB_per_s": round(n * ins_b / ti / 1e6, 1),
+                                      "frac": round(n * ins_b / ti / 1e6 / HBM_PEAK_GBS, 4),
+                                      "line_reads_G_per_s": round(n * ins_l / ti / 1e6, 2)},
+                           "find": {"bytes_per_op": round(fnd_b, 1), "GB_per_s": round(N_FIND * fnd_b / tf / 1e6, 1),
+                                    "frac": round(N_FIND * fnd_b / tf / 1e6 / HBM_PEAK_GBS, 4),
+                                    "line_reads_G_per_s": round(N_FIND * fnd_l / tf / 1e6, 2)}}}
         del t
     rows["compact_vs_plain"] = {
         "insert": round(rows["compact_16_32"]["insert_mops"] / rows["plain_64_64"]["insert_mops"], 3),

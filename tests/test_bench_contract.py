@@ -32,3 +32,24 @@ def test_percentiles():
     xs = list(range(1, 101))
     assert bench.pct(xs, 50) in (50, 51)
     assert bench.pct(xs, 99) == 99
+
+
+def test_iceberg_overflow_rates_match_the_oracle():
+    """ICE_L2 (share of inserts / finds that read both secondary buckets at
+    load 0.9) comes from the sequential oracle; recount it at a smaller shape
+    with the same buckets and load."""
+    import numpy as np
+
+    import oracle
+    import synth
+
+    L0, w = 16, 26  # 2^11 primary buckets, 15-bit remainders in 16-bit slots
+    t = oracle.Table(oracle.ICEBERG, w, L0, 32, 16, log2_slots1=L0 - 3, B1=16, s1=32, seed=11)
+    cap = (1 << L0) + (1 << (L0 - 3))
+    n = int(0.9 * cap)
+    keys = synth.distinct_keys(w, 0x5EED, 0, n).numpy().astype(np.uint64)
+    _, lput = t.insert(keys, lines=True)
+    q = synth.find_queries(w, 0x5EED, n, 1 << 15, 0.5, 3).numpy().astype(np.uint64)
+    _, lfind = t.find(q, lines=True)
+    assert abs((lput.mean() - 1) / 2 - bench.ICE_L2["put"]) < 0.01
+    assert abs((lfind.mean() - 1) / 2 - bench.ICE_L2["find"]) < 0.02
