@@ -133,17 +133,20 @@ __global__ __launch_bounds__(TPB) void sort_hist(const K* __restrict__ keys, uin
 // [w * SEG, (w + 1) * SEG) in order, 64 at a time: lanes with equal digits
 // rank by lane, and a per-wave counter per digit carries the rank across
 // rounds.  The tile is then laid out by digit in shared memory and written
-// out in order, so consecutive threads write consecutive output words.
+// out in order, so consecutive threads write consecutive output words: keys
+// first, then the positions through the same buffer (one buffer of keys and
+// a byte of digit per slot keep shared memory at 42 KB, three blocks per CU).
 template <class K>
-__global__ __launch_bounds__(TPB) void sort_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ iin,
+__global__ __launch_bounds__(TPB, 3) void sort_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ iin,
                                                     K* __restrict__ kout, uint32_t* __restrict__ iout, uint64_t n,
                                                     uint32_t shift, const uint32_t* __restrict__ offs,
                                                     uint32_t ntiles) {
   __shared__ uint32_t wc[WAVES][RADIX];
   __shared__ uint32_t dstart[RADIX];
+  __shared__ uint32_t obase[RADIX];  // output index of staged slot p with digit d: obase[d] + p
   __shared__ uint32_t tmp[WAVES + 1];
-  __shared__ K sk[TILE];
-  __shared__ uint32_t si[TILE];
+  __shared__ K stage[TILE];        // keys by digit, then (as uint32) their input positions
+  __shared__ uint8_t sdig[TILE];   // digit of each staged slot
   const uint64_t tile = tile_of_block(ntiles);
   if (tile >= ntiles) return;
   const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
@@ -154,7 +157,7 @@ __global__ __launch_bounds__(TPB) void sort_scatter(const K* __restrict__ kin, c
   const uint64_t seg = tbase + (uint64_t)wv * SEG;
   const uint64_t below = (1ull << lane) - 1ull;
   K key[IPT];
-  uint32_t rank[IPT];
+  uint32_t pos[IPT];  // rank among the wave's keys of the same digit, then slot in the tile
 #pragma unroll
   for (int r = 0; r < IPT; ++r) {
     const uint64_t i = seg + (uint64_t)r * 64 + lane;
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(TPB) void sort_scatter(const K* __restrict__ kin, c
     volatile uint32_t* ctr = &wc[wv][d];
     const uint32_t b = valid ? *ctr : 0u;
     if (valid && (peers & below) == 0ull) *ctr = b + (uint32_t)__popcll(peers);
-    rank[r] = b + (uint32_t)__popcll(peers & below);
+    pos[r] = b + (uint32_t)__popcll(peers & below);
     key[r] = k;
   }
   __syncthreads();
@@ -191,28 +194,35 @@ __global__ __launch_bounds__(TPB) void sort_scatter(const K* __restrict__ kin, c
   uint32_t all;
   const uint32_t ds = block_excl_scan(tot, tmp, &all);
   dstart[threadIdx.x] = ds;
+  // the tile's run of digit d starts at offs[d][tile] >= ds (it follows every
+  // key of a smaller digit), so the difference fits the index type
+  obase[threadIdx.x] = offs[(uint64_t)threadIdx.x * ntiles + tile] - ds;
   __syncthreads();
 
+  const uint32_t tile_n = (uint32_t)(n - tbase < (uint64_t)TILE ? n - tbase : (uint64_t)TILE);
+  // keys
 #pragma unroll
   for (int r = 0; r < IPT; ++r) {
     const uint64_t i = seg + (uint64_t)r * 64 + lane;
     if (i < n) {
       const uint32_t d = (uint32_t)(key[r] >> shift) & (RADIX - 1u);
-      const uint32_t pos = dstart[d] + wc[wv][d] + rank[r];
-      sk[pos] = key[r];
-      si[pos] = iin ? iin[i] : (uint32_t)i;
+      pos[r] += dstart[d] + wc[wv][d];
+      stage[pos[r]] = key[r];
+      sdig[pos[r]] = (uint8_t)d;
     }
   }
   __syncthreads();
-
-  const uint32_t tile_n = (uint32_t)(n - tbase < (uint64_t)TILE ? n - tbase : (uint64_t)TILE);
-  for (uint32_t p = threadIdx.x; p < tile_n; p += TPB) {
-    const K k = sk[p];
-    const uint32_t d = (uint32_t)(k >> shift) & (RADIX - 1u);
-    const uint64_t o = (uint64_t)offs[(uint64_t)d * ntiles + tile] + (p - dstart[d]);
-    kout[o] = k;
-    iout[o] = si[p];
+  for (uint32_t p = threadIdx.x; p < tile_n; p += TPB) kout[(uint64_t)obase[sdig[p]] + p] = stage[p];
+  __syncthreads();
+  // input positions, through the same buffer
+  uint32_t* sidx = reinterpret_cast<uint32_t*>(stage);
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    const uint64_t i = seg + (uint64_t)r * 64 + lane;
+    if (i < n) sidx[pos[r]] = iin ? iin[i] : (uint32_t)i;
   }
+  __syncthreads();
+  for (uint32_t p = threadIdx.x; p < tile_n; p += TPB) iout[(uint64_t)obase[sdig[p]] + p] = sidx[p];
 }
 
 // ---------------------------------------------------------------------------
@@ -386,6 +396,8 @@ __global__ __launch_bounds__(TPB) void final_answers(const uint32_t* __restrict_
     const uint32_t u = uniq[i];
     const uint8_t o = uo[u];
     const bool head = i == 0 || uniq[i - 1] != u;
+    // one byte to a random place; a plain store, so the cache merges the
+    // bytes that land in one line (a streaming store measured 1.8x slower)
     out[pos[i]] = head ? o : (o == R_PUT ? (uint8_t)R_FOUND : o);
   }
 }
