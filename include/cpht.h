@@ -202,6 +202,8 @@ cpht_status_t cpht_find_values(cpht_table_t t, const void* d_keys, uint64_t n, u
  * slot's index in cpht_export's image of that level. */
 cpht_status_t cpht_values_bytes(cpht_table_t t, uint32_t level, uint64_t* bytes);
 cpht_status_t cpht_export_values(cpht_table_t t, uint32_t level, void* h_dst, uint64_t bytes);
+/* The reverse of cpht_export_values (synchronous), for checkpoint / resume. */
+cpht_status_t cpht_import_values(cpht_table_t t, uint32_t level, const void* h_src, uint64_t bytes);
 
 /* Cuckoo only: find-or-put by sorting the batch, the baseline of the paper's
  * find-or-put experiment (Sec. 5, find-or-put benchmark): the keys are
@@ -251,6 +253,14 @@ cpht_status_t cpht_level_ptr(cpht_table_t t, uint32_t level, void** d_ptr);
  * compact).  The slab pool (level 2) uses the same slot layout with slab id i
  * at byte offset (i - 1)*128; list heads (level 3) are uint32 slab ids. */
 cpht_status_t cpht_export(cpht_table_t t, uint32_t level, void* h_dst, uint64_t bytes);
+
+/* Checkpoint / resume: copy a host image (as written by cpht_export, same
+ * configuration and seed) into image `level` (synchronous).  Restoring the
+ * slab pool (level 2) also restores the count of slabs taken, as the highest
+ * slab that holds anything (every slab taken is on a list).  The caller
+ * restores every image of the table before using it; no other call may run
+ * on the table meanwhile. */
+cpht_status_t cpht_import(cpht_table_t t, uint32_t level, const void* h_src, uint64_t bytes);
 
 /* The quotienting split of Sec. 2.4 as the table applies it: for permutation
  * `perm_index` (cuckoo: hash index j < H; iceberg: 0 = primary, 1 and 2 =

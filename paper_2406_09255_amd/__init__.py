@@ -79,6 +79,8 @@ _SIGNATURES = {
     "cpht_find_values": (_I32, [_VP, _VP, _U64, _VP, _VP, _VP]),
     "cpht_values_bytes": (_I32, [_VP, _U32, ctypes.POINTER(_U64)]),
     "cpht_export_values": (_I32, [_VP, _U32, _VP, _U64]),
+    "cpht_import_values": (_I32, [_VP, _U32, _VP, _U64]),
+    "cpht_import": (_I32, [_VP, _U32, _VP, _U64]),
     "cpht_sorted_fop": (_I32, [_VP, _VP, _U64, _VP, _VP, _U64, _VP]),
     "cpht_sorted_fop_workspace": (_I32, [_VP, _U64, ctypes.POINTER(_U64)]),
     "cpht_count": (_I32, [_VP, ctypes.POINTER(_U64), ctypes.POINTER(_U64), _VP]),
@@ -328,6 +330,36 @@ class Table:
         _check(lib().cpht_find_values(self._h, self._keys(keys), n, _dev_ptr(found, "found"),
                                       self._values(values, n), _stream(stream)), "cpht_find_values")
         return found, values
+
+    def import_image(self, level: int, image) -> None:
+        """Restore image `level` from a host array written by export (checkpoint / resume)."""
+        import numpy as np  # host staging buffer only
+
+        buf = np.ascontiguousarray(image, dtype=np.uint8)
+        _check(lib().cpht_import(self._h, level, buf.ctypes.data_as(_VP), buf.size), "cpht_import")
+
+    def import_values(self, level: int, values) -> None:
+        import numpy as np  # host staging buffer only
+
+        buf = np.ascontiguousarray(values, dtype=np.uint8)
+        _check(lib().cpht_import_values(self._h, level, buf.ctypes.data_as(_VP), buf.size), "cpht_import_values")
+
+    def checkpoint(self) -> dict:
+        """Configuration and every image (and value array) in host memory."""
+        state = {"config": self.config.as_dict(), "images": [self.export(x) for x in range(self.nimages)]}
+        if self.config.value_bytes:
+            state["values"] = [self.export_values(x) for x in range(3 if self.config.pool_slabs else 2)]
+        return state
+
+    @classmethod
+    def restore(cls, state: dict) -> "Table":
+        """A new table with the checkpoint's configuration and contents."""
+        t = cls(**state["config"])
+        for x, img in enumerate(state["images"]):
+            t.import_image(x, img)
+        for x, v in enumerate(state.get("values", [])):
+            t.import_values(x, v)
+        return t
 
     def export_values(self, level: int):
         """Value array of level 0, 1 or 2 (third-level pool) in host memory (numpy uint8)."""

@@ -528,6 +528,38 @@ cpht_status_t cpht_export(cpht_table_t t, uint32_t level, void* h_dst, uint64_t 
   return device_status(e);
 }
 
+cpht_status_t cpht_import(cpht_table_t t, uint32_t level, const void* h_src, uint64_t bytes) {
+  if (!t || !h_src || level >= (uint32_t)t->nimages || bytes != t->level_words[level] * 4) return CPHT_E_ARG;
+  DeviceGuard g(t->device);
+  if (!g.ok) return CPHT_E_DEVICE;
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(t->level[level], h_src, bytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess && level == 2) {
+    // slabs are taken in id order and each one taken is on a list, so the
+    // count taken is the highest slab holding a nonzero word
+    const uint32_t* w = static_cast<const uint32_t*>(h_src);
+    uint32_t used = 0;
+    for (uint64_t i = t->level_words[2]; i-- > 0;)
+      if (w[i]) {
+        used = (uint32_t)(i / 32 + 1);
+        break;
+      }
+    e = hipMemcpy(t->l3_used, &used, sizeof(used), hipMemcpyHostToDevice);
+  }
+  return device_status(e);
+}
+
+cpht_status_t cpht_import_values(cpht_table_t t, uint32_t level, const void* h_src, uint64_t bytes) {
+  if (!t || !h_src || level > 2) return CPHT_E_ARG;
+  if (!t->vals[level]) return CPHT_E_STATE;
+  if (bytes != t->val_bytes[level]) return CPHT_E_ARG;
+  DeviceGuard g(t->device);
+  if (!g.ok) return CPHT_E_DEVICE;
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(t->vals[level], h_src, bytes, hipMemcpyHostToDevice);
+  return device_status(e);
+}
+
 cpht_status_t cpht_split(cpht_table_t t, uint32_t perm_index, const void* d_keys, uint64_t n, uint64_t* d_addr,
                          uint64_t* d_stored, void* stream) {
   if (!t) return CPHT_E_ARG;
