@@ -386,6 +386,11 @@ class Table:
         need = self.sorted_fop_workspace(n)
         if workspace is None:
             workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=keys.device)
+            if stream is not None:
+                # allocated on the current stream, used on `stream`: keep the caching
+                # allocator from handing it out again before `stream` is done with it
+                s = stream if isinstance(stream, torch.cuda.Stream) else torch.cuda.ExternalStream(stream)
+                workspace.record_stream(s)
         if workspace.dtype != torch.uint8 or workspace.numel() < need:
             raise ValueError(f"workspace must be a uint8 device tensor of at least {need} bytes")
         _check(lib().cpht_sorted_fop(self._h, self._keys(keys), n, _dev_ptr(out, "out"),
