@@ -334,7 +334,11 @@ cpht_status_t cpht_multi_error(cpht_multi_t m, uint32_t* flags);
  * may therefore answer either way; every other answer equals the answer the
  * request gets alone.  Host buffers passed to the server should be pinned
  * (page-locked) for asynchronous copies and must stay valid until the request
- * completes.  Latency = completion time - submission time (steady clock). */
+ * completes.  Latency = completion time - submission time (steady clock).
+ * The table must outlive the server.  The server keeps a small record (about
+ * 48 bytes) per ticket until it stops.  After a device error every pending and
+ * later request completes at once (results undefined) and submit, poll and
+ * wait return CPHT_E_DEVICE. */
 typedef struct cpht_server* cpht_server_t;
 
 typedef struct {

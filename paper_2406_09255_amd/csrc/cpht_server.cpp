@@ -160,10 +160,10 @@ hipError_t launch_group(cpht_server* s, Slot& slot, uint64_t begin, const std::v
 }
 
 void dispatcher(cpht_server* s) {
-  if (hipSetDevice(s->table->device) != hipSuccess) {
-    s->error = 1;
-    return;
-  }
+  // On a device failure the loop below still runs: it admits nothing, completes
+  // every queued request at once and exits when the server stops, so waiters
+  // never block on a dispatcher that is gone.
+  if (hipSetDevice(s->table->device) != hipSuccess) s->error = 1;
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
     bool inflight = false;

@@ -350,6 +350,52 @@ def test_single_bucket_levels(gpu):
     assert np.array_equal(f, (out == cpht.PUT).astype(np.uint8))
 
 
+def test_zero_bit_remainders(gpu):
+    """The address takes every key bit (w = log2 #buckets, so the remainder
+    has no bits, Sec. 2.4): a slot then holds only the occupancy bit and the
+    hash tag, and since each permutation is a bijection every key owns its
+    own primary (iceberg) or first (cuckoo) bucket.  The whole key domain
+    goes in with PUT, no key moves or overflows, and every lookup hits."""
+    w = 10
+    keys = synth.distinct_keys(w, KEY_SEED, 0, 1 << w)
+    dk = to_dev(keys, w, gpu)
+    t = iceberg(w, 15, 32, 16, 16, log2_slots1=12)  # 2^10 primary buckets
+    o = oracle_table(t)
+    out = t.insert(dk).cpu().numpy()
+    assert (out == cpht.PUT).all() and (o.insert(host_u64(keys)) == oracle.PUT).all()
+    assert np.array_equal(check_table(t), np.arange(1 << w, dtype=np.uint64))
+    for got, want in zip(images(t), [o.export(0), o.export(1)]):
+        assert np.array_equal(got, want)  # the placement is forced: images are bit-exact
+    assert (t.insert(dk).cpu().numpy() == cpht.FOUND).all()
+    assert (t.find(dk).cpu().numpy() == 1).all()
+    c = cuckoo(w, 15, 32, 32)  # 2^10 buckets of 32 slots
+    oc = oracle_table(c)
+    assert (c.bulk_build(dk).cpu().numpy() == cpht.PUT).all()
+    oc.insert(host_u64(keys))
+    assert np.array_equal(images(c)[0], oc.export(0))
+    assert (c.find(dk).cpu().numpy() == 1).all()
+
+
+@pytest.mark.parametrize("scheme", ["cuckoo", "iceberg"])
+def test_full_width_64_bit_keys(gpu, scheme):
+    """w = 64: keys use every bit of their word (the permutations work mod
+    2^64); compact 64-bit slots store the 64 - log2 #buckets remainder bits."""
+    w = 64
+    if scheme == "cuckoo":
+        t = cuckoo(w, 16, 16, 64)
+    else:
+        t = iceberg(w, 16, 32, 64, 64, log2_slots1=13)
+    o = oracle_table(t)
+    keys = synth.distinct_keys(w, KEY_SEED, 0, int(0.85 * (1 << 16)))
+    kh = host_u64(keys)
+    assert (kh >> np.uint64(63)).any()  # keys with the top bit set are in the batch
+    out = (t.bulk_build if scheme == "cuckoo" else t.insert)(to_dev(keys, w, gpu)).cpu().numpy()
+    assert (out == cpht.PUT).all() and (o.insert(kh) == oracle.PUT).all()
+    assert np.array_equal(check_table(t), np.sort(kh))
+    q = synth.find_queries(w, KEY_SEED, kh.size, 30000, 0.5, 9)
+    assert np.array_equal(t.find(to_dev(q, w, gpu)).cpu().numpy(), o.find(host_u64(q)))
+
+
 def test_clear_and_reseed(gpu):
     w = 32
     t = cuckoo(w, 16, 32, 32, seed=1)

@@ -275,6 +275,27 @@ def test_cuckoo_brute_force_tiny_domain():
     assert np.array_equal(t.find(domain), np.isin(domain, dec).astype(np.uint8))
 
 
+def test_zero_bit_remainder_images_are_forced():
+    """When the bucket address takes all w key bits the remainder is empty
+    and each permutation is a bijection onto the buckets, so the whole domain
+    fills exactly slot 0 of every primary (first-hash) bucket with the bare
+    occupancy bit and hash tag 0, whatever the permutation: the images are
+    fixed without reference to the oracle's hashing."""
+    w = 10
+    t = oracle.Table(oracle.ICEBERG, w, 15, 32, 16, log2_slots1=12, B1=16, s1=16, seed=3)
+    domain = np.arange(1 << w, dtype=np.uint64)
+    assert (t.insert(_rng(4).permutation(domain)) == oracle.PUT).all()
+    img0 = t.export(0).view(np.uint16).reshape(1 << w, 32)
+    assert (img0[:, 0] == 0x8000).all() and (img0[:, 1:] == 0).all()
+    assert (t.export(1) == 0).all()
+    assert (t.insert(domain) == oracle.FOUND).all() and (t.find(domain) == 1).all()
+    c = oracle.Table(oracle.CUCKOO, w, 15, 32, 32, seed=4)
+    assert (c.insert(_rng(5).permutation(domain)) == oracle.PUT).all()
+    img = c.export(0).view(np.uint32).reshape(1 << w, 32)
+    assert (img[:, 0] == 0x80000000).all() and (img[:, 1:] == 0).all()
+    assert (c.find(domain) == 1).all()
+
+
 # ---------------------------------------------------------------------------
 # line counts (the per-operation bucket reads used for the roofline)
 # ---------------------------------------------------------------------------
