@@ -803,6 +803,7 @@ def serving(torch, cpht, synth, dev, n_req=20000, log2_slots0=32, prefill=0.5, s
 
     cont = dict(max_inflight=4, coalesce=1, staging_keys=1 << 25, max_batch_keys=1 << 22)
     plain = dict(max_inflight=1, coalesce=0, staging_keys=1 << 25, max_batch_keys=1 << 22)
+    direct = dict(max_inflight=4, coalesce=1, max_batch_keys=1 << 22, zero_copy=1)
     res = {"config": (f"iceberg 2^{L0} + 2^{L1} slots (16/32-bit, {t.level_bytes(0) + t.level_bytes(1)} bytes), "
                       f"{w}-bit keys, pre-filled to load {prefill}; {n_req} requests, {total} operations, sizes "
                       f"lognormal(median 4096, sigma 2) in 1..2^22, 70% find / 30% insert, pinned host buffers"),
@@ -810,16 +811,50 @@ def serving(torch, cpht, synth, dev, n_req=20000, log2_slots0=32, prefill=0.5, s
     zero = np.zeros(n_req, dtype=np.uint64)
     res["saturated"] = run(zero, **cont)
     res["saturated_plain"] = run(zero, **plain)
+    res["saturated_zero_copy"] = run(zero, **direct)
     rate = res["saturated"]["requests_per_s"]
     for frac in (0.25, 0.5, 0.75, 0.9):
         gaps = r.exponential(1e9 / (frac * rate), n_req)
         arrival = np.cumsum(gaps).astype(np.uint64)
         res[f"poisson_{int(frac * 100)}"] = run(arrival, **cont)
         res[f"poisson_{int(frac * 100)}_plain"] = run(arrival, **plain)
+        res[f"poisson_{int(frac * 100)}_zero_copy"] = run(arrival, **direct)
+    # every operation moves its key and opcode to the device and its answer
+    # back over the host link; the inbound direction binds
+    kb = t.key_dtype.itemsize
+    link = host_link(torch, dev)
+    res["host_link"] = dict(link, bytes_in_per_op=kb + 1, bytes_out_per_op=1)
+    for name in ("saturated", "saturated_zero_copy"):
+        gbs = res[name]["mops"] * 1e6 * (kb + 1) / 1e9
+        res[name]["host_link_in_GBps"] = round(gbs, 2)
+        res[name]["frac_of_h2d"] = round(gbs / link["h2d_GBps"], 3)
     occ, cp = t.count()
     res["fill_factor_end"] = round(occ / cp, 4)
     del t
     return res
+
+
+def host_link(torch, dev, mib=512, reps=5):
+    """Copy rates between pinned host memory and the device (one 512 MiB
+    transfer per direction, best of 5): the ceiling of any path whose
+    operations cross the host link."""
+    n = mib << 20
+    h = torch.empty(n, dtype=torch.uint8).pin_memory()
+    d = torch.empty(n, dtype=torch.uint8, device=dev)
+    out = {}
+    for name, dst, src in (("h2d_GBps", d, h), ("d2h_GBps", h, d)):
+        best = None
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            dst.copy_(src, non_blocking=True)
+            b.record()
+            b.synchronize()
+            ms = a.elapsed_time(b)
+            best = ms if best is None else min(best, ms)
+        out[name] = round(n / (best / 1e3) / 1e9, 2)
+    del h, d
+    return out
 
 
 def ceilings(torch, cpht, dev, res):

@@ -335,8 +335,13 @@ cpht_status_t cpht_multi_error(cpht_multi_t m, uint32_t* flags);
  * request gets alone.  Host buffers passed to the server should be pinned
  * (page-locked) for asynchronous copies and must stay valid until the request
  * completes.  Latency = completion time - submission time (steady clock).
+ * In zero-copy mode (zero_copy = 1) there is no staging: every request buffer
+ * must be pinned host memory mapped for the device (hipHostMalloc, or a torch
+ * tensor after pin_memory()), the mixed kernel reads the keys and opcodes and
+ * writes the results in place, and a launch covers a run of queued requests
+ * that lie back to back in all three buffers (up to max_batch_keys keys).
  * The table must outlive the server.  The server keeps a small record (about
- * 48 bytes) per ticket until it stops.  After a device error every pending and
+ * 72 bytes) per ticket until it stops.  After a device error every pending and
  * later request completes at once (results undefined) and submit, poll and
  * wait return CPHT_E_DEVICE. */
 typedef struct cpht_server* cpht_server_t;
@@ -345,10 +350,13 @@ typedef struct {
     uint32_t max_inflight;    /* concurrent launches (streams), 1..64 */
     uint32_t coalesce;        /* 1: pack several requests per launch; 0: one request per launch */
     uint64_t staging_keys;    /* device staging capacity in keys (a request must fit it) */
-    uint64_t max_batch_keys;  /* keys per launch when coalescing (<= staging_keys) */
+    uint64_t max_batch_keys;  /* keys per launch when coalescing (<= staging_keys unless zero_copy) */
+    uint32_t zero_copy;       /* 1: the device works on the pinned request buffers in place (no staging) */
+    uint32_t pad;             /* must be 0 */
 } cpht_server_config_t;
 
-/* Defaults: 4 launches in flight, coalescing, 2^24 staging keys, 2^22 keys per launch. */
+/* Defaults: 4 launches in flight, coalescing, 2^24 staging keys, 2^22 keys per
+ * launch, staged (zero_copy = 0). */
 void cpht_server_config_default(cpht_server_config_t* cfg);
 
 /* Start a server on an iceberg table (CPHT_E_STATE for cuckoo: static). */
@@ -357,7 +365,8 @@ cpht_status_t cpht_server_start(cpht_table_t t, const cpht_server_config_t* cfg,
 /* Queue a request of n operations (h_ops[i]: CPHT_OP_FIND or CPHT_OP_INSERT);
  * results go to h_out (find 0/1, insert PUT/FOUND/FULL).  Returns a ticket.
  * CPHT_E_BUSY if 2^20 requests are already queued; CPHT_E_ARG if n exceeds
- * the staging capacity. */
+ * the staging capacity or, in zero-copy mode, if a buffer is not pinned host
+ * memory mapped for the device. */
 cpht_status_t cpht_server_submit(cpht_server_t s, const void* h_keys, const uint8_t* h_ops, uint64_t n,
                                  uint8_t* h_out, uint64_t* ticket);
 

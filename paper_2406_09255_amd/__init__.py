@@ -503,6 +503,8 @@ class ServerConfig(ctypes.Structure):
         ("coalesce", ctypes.c_uint32),
         ("staging_keys", ctypes.c_uint64),
         ("max_batch_keys", ctypes.c_uint64),
+        ("zero_copy", ctypes.c_uint32),
+        ("pad", ctypes.c_uint32),
     ]
 
 
@@ -514,8 +516,9 @@ def _host_ptr(t, name: str) -> int:
 
 class Server:
     """Continuous-batching request loop over one iceberg table (cpht_server_t).
-    Request buffers are host tensors (pinned: tensor.pin_memory()) that must
-    stay alive until the request completes."""
+    Request buffers are host tensors (pinned: tensor.pin_memory(); required
+    with zero_copy=1, where the device reads and writes them in place) that
+    must stay alive until the request completes."""
 
     def __init__(self, table: Table, **fields):
         cfg = ServerConfig()

@@ -10,6 +10,11 @@
 // event.  Requests that arrive while earlier launches are on the device are
 // admitted into the next free slot, so up to max_inflight launches overlap.
 // Completed launches free their staging space and complete their requests.
+//
+// Zero-copy mode (cfg.zero_copy = 1): request buffers are pinned host memory
+// that the device reads and writes directly, so a launch is one mixed kernel
+// over the host buffers and no staging or copies are involved.  A launch then
+// covers a run of queued requests that lie back to back in all three buffers.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -40,6 +45,9 @@ struct Request {
   const uint8_t* ops;
   uint8_t* out;
   uint64_t n;
+  const void* dkeys;  // device views of the host buffers (zero-copy mode)
+  const uint8_t* dops;
+  uint8_t* dout;
   uint64_t t_submit;
   uint64_t t_done;  // 0 while pending
 };
@@ -159,6 +167,41 @@ hipError_t launch_group(cpht_server* s, Slot& slot, uint64_t begin, const std::v
   return hipEventRecord(slot.done, st);
 }
 
+// Zero-copy launch: one mixed kernel over a run of requests that lie back to
+// back in the host buffers (their device views are contiguous as well).
+hipError_t launch_direct(cpht_server* s, Slot& slot, const Request& first, uint64_t n) {
+  const cpht_status_t cs = cpht_mixed(s->table, first.dkeys, first.dops, n, first.dout, slot.stream);
+  if (cs != CPHT_OK) return hipErrorLaunchFailure;
+  return hipEventRecord(slot.done, slot.stream);
+}
+
+bool adjacent(const Request& a, const Request& b, uint64_t key_bytes) {
+  return static_cast<const char*>(b.dkeys) == static_cast<const char*>(a.dkeys) + a.n * key_bytes &&
+         b.dops == a.dops + a.n && b.dout == a.dout + a.n;
+}
+
+// Device view of a pinned host range [h, h + bytes); nullptr unless both ends
+// lie in pinned host memory mapped for the device with the same offset
+// between host and device addresses.
+bool host_mapping(const void* p, intptr_t* delta) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();  // an unknown (pageable) pointer leaves an error behind
+    return false;
+  }
+  if (a.type != hipMemoryTypeHost || !a.devicePointer || !a.hostPointer) return false;
+  *delta = static_cast<const char*>(a.devicePointer) - static_cast<const char*>(a.hostPointer);
+  return true;
+}
+
+template <class T>
+T* device_view(T* h, uint64_t bytes) {
+  const char* b = reinterpret_cast<const char*>(h);
+  intptr_t d0 = 0, d1 = 0;
+  if (!host_mapping(b, &d0) || !host_mapping(b + bytes - 1, &d1) || d0 != d1) return nullptr;
+  return reinterpret_cast<T*>(const_cast<char*>(b) + d0);
+}
+
 void dispatcher(cpht_server* s) {
   // On a device failure the loop below still runs: it admits nothing, completes
   // every queued request at once and exits when the server stops, so waiters
@@ -184,7 +227,7 @@ void dispatcher(cpht_server* s) {
         s->ops_done += s->reqs[id].n;
         ++s->reqs_done;
       }
-      ring_release(s, sl.ring_begin + sl.ring_len);
+      if (!s->cfg.zero_copy) ring_release(s, sl.ring_begin + sl.ring_len);
       sl.busy = false;
       sl.reqs.clear();
       s->cv.notify_all();
@@ -192,6 +235,30 @@ void dispatcher(cpht_server* s) {
     // 2. admit queued requests into free slots while staging has room
     for (Slot& sl : s->slots) {
       if (sl.busy || s->queue.empty() || s->error) continue;
+      if (s->cfg.zero_copy) {  // a run of back-to-back requests, read and written in place
+        std::vector<uint64_t> ids{s->queue.front()};
+        s->queue.pop_front();
+        uint64_t total = s->reqs[ids[0]].n;
+        while (s->cfg.coalesce && !s->queue.empty()) {
+          const Request& last = s->reqs[ids.back()];
+          const Request& next = s->reqs[s->queue.front()];
+          if (total + next.n > s->cfg.max_batch_keys || !adjacent(last, next, s->key_bytes)) break;
+          ids.push_back(s->queue.front());
+          total += next.n;
+          s->queue.pop_front();
+        }
+        sl.busy = true;
+        sl.ring_begin = sl.ring_len = 0;
+        sl.reqs = ids;
+        const Request first = s->reqs[ids[0]];  // the request table may grow while unlocked
+        lk.unlock();
+        const hipError_t e = launch_direct(s, sl, first, total);
+        lk.lock();
+        if (e != hipSuccess) s->error = 1;
+        ++s->launches;
+        inflight = true;
+        continue;
+      }
       std::vector<uint64_t> ids;
       uint64_t total = 0;
       while (!s->queue.empty()) {
@@ -269,26 +336,31 @@ void cpht_server_config_default(cpht_server_config_t* c) {
   c->coalesce = 1;
   c->staging_keys = 1ull << 24;
   c->max_batch_keys = 1ull << 22;
+  c->zero_copy = 0;
+  c->pad = 0;
 }
 
 cpht_status_t cpht_server_start(cpht_table_t t, const cpht_server_config_t* cfg, cpht_server_t* out) {
   if (!t || !cfg || !out) return CPHT_E_ARG;
   *out = nullptr;
   if (!t->ice) return CPHT_E_STATE;  // the dynamic (iceberg) table only
-  if (cfg->max_inflight < 1 || cfg->max_inflight > 64 || cfg->staging_keys < 1 || cfg->max_batch_keys < 1 ||
-      cfg->max_batch_keys > cfg->staging_keys)
+  if (cfg->max_inflight < 1 || cfg->max_inflight > 64 || cfg->max_batch_keys < 1 || cfg->zero_copy > 1 ||
+      cfg->pad != 0)
     return CPHT_E_ARG;
+  if (!cfg->zero_copy && (cfg->staging_keys < 1 || cfg->max_batch_keys > cfg->staging_keys)) return CPHT_E_ARG;
   cpht_server* s = new (std::nothrow) cpht_server();
   if (!s) return CPHT_E_NOMEM;
   s->table = t;
   s->cfg = *cfg;
   s->key_bytes = t->cfg.key_bits > 32 ? 8 : 4;
-  s->ring_cap = cfg->staging_keys;
+  s->ring_cap = cfg->zero_copy ? 0 : cfg->staging_keys;
   DeviceGuard g(t->device);
   hipError_t e = g.ok ? hipSuccess : hipErrorInvalidDevice;
-  if (e == hipSuccess) e = hipMalloc(&s->d_keys, s->ring_cap * s->key_bytes);
-  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s->d_ops), s->ring_cap);
-  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s->d_out), s->ring_cap);
+  if (!cfg->zero_copy) {  // the device staging ring
+    if (e == hipSuccess) e = hipMalloc(&s->d_keys, s->ring_cap * s->key_bytes);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s->d_ops), s->ring_cap);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s->d_out), s->ring_cap);
+  }
   s->slots.resize(cfg->max_inflight);
   for (Slot& sl : s->slots) {
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
@@ -305,13 +377,22 @@ cpht_status_t cpht_server_start(cpht_table_t t, const cpht_server_config_t* cfg,
 
 cpht_status_t cpht_server_submit(cpht_server_t s, const void* h_keys, const uint8_t* h_ops, uint64_t n,
                                  uint8_t* h_out, uint64_t* ticket) {
+  const uint64_t t_call = now_ns();  // latency counts the submission work too
   if (!s || !ticket || (n && (!h_keys || !h_ops || !h_out))) return CPHT_E_ARG;
-  if (n > s->cfg.staging_keys) return CPHT_E_ARG;  // could never be admitted
+  if (!s->cfg.zero_copy && n > s->cfg.staging_keys) return CPHT_E_ARG;  // could never be admitted
+  Request r{h_keys, h_ops, h_out, n, nullptr, nullptr, nullptr, 0, 0};
+  if (s->cfg.zero_copy && n) {  // the device reads and writes the host buffers in place
+    DeviceGuard g(s->table->device);
+    r.dkeys = device_view(h_keys, n * s->key_bytes);
+    r.dops = device_view(h_ops, n);
+    r.dout = device_view(h_out, n);
+    if (!r.dkeys || !r.dops || !r.dout) return CPHT_E_ARG;
+  }
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stopping) return CPHT_E_STATE;
   if (s->error) return CPHT_E_DEVICE;
   if (s->queue.size() >= (1u << 20)) return CPHT_E_BUSY;
-  Request r{h_keys, h_ops, h_out, n, now_ns(), 0};
+  r.t_submit = t_call;
   *ticket = s->reqs.size();
   s->reqs.push_back(r);
   if (n == 0) {

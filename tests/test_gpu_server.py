@@ -56,8 +56,22 @@ def _prefill(t, gpu, n):
     return np.sort(host_u64(keys))
 
 
-def _run(server, reqs, wait_each=False):
-    outs = [torch.zeros(k.numel(), dtype=torch.uint8).pin_memory() for k, _ in reqs]
+def _packed(reqs):
+    """The same requests as views of one pinned buffer per field, back to back
+    in arrival order (what zero-copy launches coalesce)."""
+    keys = torch.cat([k for k, _ in reqs]).pin_memory()
+    ops = torch.cat([o for _, o in reqs]).pin_memory()
+    cuts = np.cumsum([0] + [k.numel() for k, _ in reqs])
+    return [(keys[a:b], ops[a:b]) for a, b in zip(cuts[:-1], cuts[1:])]
+
+
+def _run(server, reqs, wait_each=False, packed=False):
+    if packed:  # packed requests get packed outputs
+        buf = torch.zeros(sum(k.numel() for k, _ in reqs), dtype=torch.uint8).pin_memory()
+        cuts = np.cumsum([0] + [k.numel() for k, _ in reqs])
+        outs = [buf[a:b] for a, b in zip(cuts[:-1], cuts[1:])]
+    else:
+        outs = [torch.zeros(k.numel(), dtype=torch.uint8).pin_memory() for k, _ in reqs]
     lat = []
     if wait_each:
         for (k, o), out in zip(reqs, outs):
@@ -68,18 +82,23 @@ def _run(server, reqs, wait_each=False):
     return [o.numpy().copy() for o in outs], lat
 
 
-def test_server_alone_equals_mix(gpu):
+@pytest.mark.parametrize("zero_copy", [0, 1])
+def test_server_alone_equals_mix(gpu, zero_copy):
     pre = 50000
     reqs = _requests(120, pre, 1, pre)
+    if zero_copy:
+        reqs = _packed(reqs)
     t_mix, t_alone = _table(), _table()
     S0 = _prefill(t_mix, gpu, pre)
     _prefill(t_alone, gpu, pre)
-    mix = cpht.Server(t_mix, max_inflight=4, coalesce=1, staging_keys=1 << 16, max_batch_keys=1 << 14)
-    out_mix, lat = _run(mix, reqs)
+    mix = cpht.Server(t_mix, max_inflight=4, coalesce=1, staging_keys=1 << 16, max_batch_keys=1 << 14,
+                      zero_copy=zero_copy)
+    out_mix, lat = _run(mix, reqs, packed=bool(zero_copy))
     st = mix.stats()
     mix.stop()
-    alone = cpht.Server(t_alone, max_inflight=1, coalesce=0, staging_keys=1 << 16, max_batch_keys=1 << 14)
-    out_alone, _ = _run(alone, reqs, wait_each=True)
+    alone = cpht.Server(t_alone, max_inflight=1, coalesce=0, staging_keys=1 << 16, max_batch_keys=1 << 14,
+                        zero_copy=zero_copy)
+    out_alone, _ = _run(alone, reqs, wait_each=True, packed=bool(zero_copy))
     alone.stop()
     assert st["requests_done"] == len(reqs) and st["launches"] < len(reqs)  # requests were coalesced
     S = S0
@@ -141,7 +160,8 @@ def test_server_admission_waits_for_staging(gpu):
         assert np.array_equal(res[f], want[f])
 
 
-def test_server_trace_replay(gpu):
+@pytest.mark.parametrize("zero_copy", [0, 1])
+def test_server_trace_replay(gpu, zero_copy):
     pre = 30000
     reqs = _requests(200, pre, 4, pre)
     t = _table(24)
@@ -151,7 +171,7 @@ def test_server_trace_replay(gpu):
     out = torch.zeros(keys.numel(), dtype=torch.uint8).pin_memory()
     offsets = np.concatenate([[0], np.cumsum([k.numel() for k, _ in reqs])]).astype(np.uint64)
     arrival = (np.cumsum(np.random.default_rng(5).exponential(20000.0, len(reqs)))).astype(np.uint64)
-    srv = cpht.Server(t)
+    srv = cpht.Server(t, zero_copy=zero_copy)
     lat, makespan = srv.replay(arrival, offsets, keys, ops, out)
     srv.stop()
     assert (lat > 0).all() and makespan >= arrival[-1]
@@ -168,3 +188,19 @@ def test_server_needs_dynamic_table(gpu):
     c = cpht.Table(scheme=cpht.CUCKOO, key_bits=32, log2_slots0=12, bucket0=32, slot_bits0=32)
     with pytest.raises(cpht.CphtError):
         cpht.Server(c)
+
+
+def test_server_zero_copy_needs_pinned_buffers(gpu):
+    t = _table(25)
+    srv = cpht.Server(t, zero_copy=1)
+    keys = synth.to_words(synth.feistel(W, 77, torch.arange(100, dtype=torch.int64)), W)
+    ops = torch.zeros(100, dtype=torch.uint8)
+    out = torch.zeros(100, dtype=torch.uint8)
+    with pytest.raises(cpht.CphtError):  # pageable host memory: the device cannot read it in place
+        srv.submit(keys, ops, out)
+    pk, po, pout = keys.pin_memory(), ops.pin_memory(), out.pin_memory()
+    with pytest.raises(cpht.CphtError):  # one pageable buffer is enough to refuse
+        srv.submit(pk, po, out)
+    srv.wait(srv.submit(pk, po, pout))
+    assert (pout.numpy() == 0).all()  # an empty table finds nothing
+    srv.stop()
