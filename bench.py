@@ -819,6 +819,26 @@ def serving(torch, cpht, synth, dev, n_req=20000, log2_slots0=32, prefill=0.5, s
         res[f"poisson_{int(frac * 100)}"] = run(arrival, **cont)
         res[f"poisson_{int(frac * 100)}_plain"] = run(arrival, **plain)
         res[f"poisson_{int(frac * 100)}_zero_copy"] = run(arrival, **direct)
+    # one 4096-operation request at a time on an idle server, beside a bare
+    # mixed launch over device-resident buffers (launch + kernel + synchronise)
+    import time
+    nq = 4096
+    kq, oq, rq = keys[:nq], ops[:nq], out[:nq]
+    kd, od = kq.to(dev), oq.to(dev)
+    rd = torch.empty(nq, dtype=torch.uint8, device=dev)
+    bare = []
+    for _ in range(300):
+        a = time.perf_counter_ns()
+        t.mixed(kd, od, out=rd)
+        torch.cuda.synchronize()
+        bare.append(time.perf_counter_ns() - a)
+    idle = {"bare_launch_device_buffers": bare}
+    for name, kw in (("staged", cont), ("zero_copy", direct)):
+        srv = cpht.Server(t, **kw)
+        idle[name] = [srv.wait(srv.submit(kq, oq, rq)) for _ in range(300)]
+        srv.stop()
+    res["idle_request_4096_us"] = {k: {"p50": round(float(np.percentile(v, 50)) / 1e3, 1),
+                                       "p99": round(float(np.percentile(v, 99)) / 1e3, 1)} for k, v in idle.items()}
     # every operation moves its key and opcode to the device and its answer
     # back over the host link; the inbound direction binds
     kb = t.key_dtype.itemsize
