@@ -215,7 +215,7 @@ class Table:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and callable(lib):  # module globals may already be gone at interpreter exit
             lib().or_free(h)
             self._h = None
 
