@@ -912,6 +912,14 @@ def ceilings(torch, cpht, dev, res):
     return out
 
 
+_T0 = time.perf_counter()
+
+
+def progress(name: str):
+    """One line per finished section on stderr (the JSON line stays alone on stdout)."""
+    print(f"[bench] {name} done at {time.perf_counter() - _T0:.1f} s", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -1046,6 +1054,7 @@ def main():
     res["roofline"] = dict(rl[dom], kernel=dom)
     res["roofline_other"] = {k: v for k, v in rl.items() if k != dom}
     del compact
+    progress("headline")
 
     if not args.no_plain:
         plain = cpht.Table(scheme=cpht.CUCKOO, key_bits=W_KEY, log2_slots0=LOG2_SLOTS, bucket0=BUCKET,
@@ -1075,12 +1084,15 @@ def main():
             "memory": round(res["table_bytes"] / res["plain"]["table_bytes"], 3),
         }
         del plain, prun
+        progress("plain")
 
     if not args.no_plain and not args.no_equal:
         res["equal_memory"] = equal_memory(torch, cpht, keys, queries, n_ins)
+        progress("equal_memory")
 
     if not args.no_window:
         res["marginal_window"] = marginal_window(torch, cpht, keys, n_ins)
+        progress("marginal_window")
 
     if not args.no_sweep:
         loads = (0.5, 0.7, 0.8, 0.9, 0.95)
@@ -1109,35 +1121,47 @@ def main():
             del t, r
         del qs
         res["sweep"] = sweep
+        progress("sweep")
 
     if not args.no_small:
         res["small_cuckoo"] = small_cuckoo(torch, cpht, synth, dev)
+        progress("small_cuckoo")
 
     if not args.no_iceberg:
         res["iceberg_static"] = iceberg_static(torch, cpht, synth, dev)
+        progress("iceberg_static")
         res["iceberg_mixed"] = iceberg_mixed(torch, cpht, synth, dev)
+        progress("iceberg_mixed")
         res["iceberg_zipf"] = iceberg_zipf(torch, cpht, synth, dev)
+        progress("iceberg_zipf")
 
     if not args.no_fop:
         res["find_or_put"] = find_or_put(torch, cpht, synth, dev)
+        progress("find_or_put")
 
     if not args.no_delete:
         res["delete"] = deletes(torch, cpht, synth, dev)
+        progress("delete")
 
     if not args.no_level3:
         res["level3"] = level3(torch, cpht, synth, dev)
+        progress("level3")
 
     if not args.no_map:
         res["map"] = kv_map(torch, cpht, synth, dev)
+        progress("map")
 
     if not args.no_many:
         res["many_tables"] = many_tables(torch, cpht, synth, dev)
+        progress("many_tables")
 
     if not args.no_serving:
         res["serving"] = serving(torch, cpht, synth, dev)
+        progress("serving")
 
     if not args.no_ceilings:
         res["ceilings"] = ceilings(torch, cpht, dev, res)
+        progress("ceilings")
         c = res["ceilings"]["table_size"]
         if res["roofline"]["kernel"] == "cuckoo_put":
             # one CAS per put round: the device's random line-read-then-CAS rate bounds the kernel
@@ -1149,6 +1173,7 @@ def main():
 
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline()
+        progress("cpu_baseline")
     print(json.dumps(res))
 
 
