@@ -433,19 +433,19 @@ class Table:
 
 class MultiTable:
     """A set of independent tables served by one launch per kernel variant
-    (cpht_multi_t).  `configs` is a list of Config; batches are CSR: the keys
+    (cpht_multi_t).  `table_configs` is a list of Config (one key width for all); batches are CSR: the keys
     of all tables concatenated plus int64 device offsets (n + 1)."""
 
-    def __init__(self, configs, max_keys: int):
-        arr = (Config * len(configs))()
-        for i, c in enumerate(configs):
+    def __init__(self, table_configs, max_keys: int):
+        arr = (Config * len(table_configs))()
+        for i, c in enumerate(table_configs):
             ctypes.memmove(ctypes.byref(arr[i]), ctypes.byref(c), ctypes.sizeof(Config))
         h = _VP()
-        _check(lib().cpht_multi_create(len(configs), ctypes.cast(arr, _VP), max_keys, ctypes.byref(h)),
+        _check(lib().cpht_multi_create(len(table_configs), ctypes.cast(arr, _VP), max_keys, ctypes.byref(h)),
                "cpht_multi_create")
         self._h = h
-        self.n = len(configs)
-        self.key_dtype = torch.int32 if configs[0].key_bits <= 32 else torch.int64
+        self.n = len(table_configs)
+        self.key_dtype = torch.int32 if table_configs[0].key_bits <= 32 else torch.int64
 
     def close(self):
         if getattr(self, "_h", None):
