@@ -58,12 +58,19 @@ TRAFFIC = {"csrc_sha": "0d93f8ec9af4f898", "cuckoo_put": 25742989235, "cuckoo_fi
 # The sources the profiled cuckoo kernels are compiled from.
 KERNEL_SOURCES = ("cpht_device.hpp", "cpht_cuckoo.hpp", "cpht_registry.hpp", "inst_cuckoo_u64.hip")
 
+# Measured HBM bytes per operation (read + written, same calibration) of the
+# iceberg kernels at the iceberg_static shape, profiles/iceberg_hbm_bytes.md;
+# valid for the iceberg sources they were taken with.
+ICE_TRAFFIC = {"src_sha": "2e7aebae9bb76098", "insert_16_32": 222.6, "find_16_32": 214.3,
+               "insert_64_64": 350.9, "find_64_64": 344.0}
+ICE_SOURCES = ("cpht_device.hpp", "cpht_iceberg.hpp", "cpht_registry.hpp", "inst_iceberg_u64.hip")
 
-def csrc_sha() -> str:
+
+def csrc_sha(sources=KERNEL_SOURCES) -> str:
     import hashlib
 
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in sources:
         h.update(name.encode())
         with open(os.path.join(ROOT, "paper_2406_09255_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
@@ -515,6 +522,12 @@ def iceberg_static(torch, cpht, synth, dev, reps=3):
                            "find": {"bytes_per_op": round(fnd_b, 1), "GB_per_s": round(N_FIND * fnd_b / tf / 1e6, 1),
                                     "frac": round(N_FIND * fnd_b / tf / 1e6 / HBM_PEAK_GBS, 4),
                                     "line_reads_G_per_s": round(N_FIND * fnd_l / tf / 1e6, 2)}}}
+        if ICE_TRAFFIC["src_sha"] == csrc_sha(ICE_SOURCES):  # measured bytes, where still valid
+            for op, nops, ms in (("insert", n, ti), ("find", N_FIND, tf)):
+                tb = ICE_TRAFFIC[f"{op}_{s0}_{s1}"]
+                rows[label]["roofline"][op].update(
+                    traffic_bytes_per_op=tb, traffic_GB_per_s=round(nops * tb / ms / 1e6, 1),
+                    traffic_frac=round(nops * tb / ms / 1e6 / HBM_PEAK_GBS, 4))
         del t
     rows["compact_vs_plain"] = {
         "insert": round(rows["compact_16_32"]["insert_mops"] / rows["plain_64_64"]["insert_mops"], 3),
