@@ -386,8 +386,11 @@ cpht_status_t cpht_server_stop(cpht_server_t s);
 /* Replay a request trace from the calling thread: request i (operations
  * [offsets[i], offsets[i+1]) of h_keys / h_ops / h_out) is submitted
  * arrival_ns[i] after the start (non-decreasing), then all are awaited.
- * latency_ns[i] receives each request's latency; *makespan_ns the time from
- * the start to the last completion. */
+ * offsets has n_requests + 1 non-decreasing entries, and the three buffers
+ * must hold offsets[n_requests] entries (not checked: the library cannot see
+ * their sizes).  latency_ns[i] receives each request's latency; *makespan_ns
+ * the time from the start to the last completion.  CPHT_E_ARG for
+ * decreasing offsets or arrival times (nothing is submitted then). */
 cpht_status_t cpht_server_replay(cpht_server_t s, uint64_t n_requests, const uint64_t* arrival_ns,
                                  const uint64_t* offsets, const void* h_keys, const uint8_t* h_ops, uint8_t* h_out,
                                  uint64_t* latency_ns, uint64_t* makespan_ns);

@@ -545,6 +545,8 @@ class Server:
     def poll(self, ticket: int):
         d, lat = _I32(0), _U64(0)
         _check(lib().cpht_server_poll(self._h, ticket, ctypes.byref(d), ctypes.byref(lat)), "cpht_server_poll")
+        if d.value:
+            self._keep.pop(ticket, None)
         return bool(d.value), lat.value
 
     def wait(self, ticket: int) -> int:
@@ -564,6 +566,14 @@ class Server:
 
         arr = np.ascontiguousarray(np.asarray(arrival_ns, dtype=np.uint64))
         off = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+        if keys.dtype != self._table.key_dtype:
+            raise ValueError(f"keys must be {self._table.key_dtype}")
+        if off.size != arr.size + 1 or (arr.size and int(off[0]) != 0):
+            raise ValueError("offsets must hold n_requests + 1 entries starting at 0")
+        if arr.size and int(off[-1]) > min(keys.numel(), ops.numel(), out.numel()):
+            raise ValueError("offsets reach past the key, opcode or result buffer")
+        if ops.dtype != torch.uint8 or out.dtype != torch.uint8:
+            raise ValueError("ops and out must be uint8")
         lat = np.zeros(arr.size, dtype=np.uint64)
         mk = _U64(0)
         _check(lib().cpht_server_replay(self._h, arr.size, arr.ctypes.data_as(_VP), off.ctypes.data_as(_VP),
