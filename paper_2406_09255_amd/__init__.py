@@ -479,6 +479,8 @@ class MultiTable:
         n = keys.numel()
         if out is None:
             out = torch.empty(n, dtype=torch.uint8, device=keys.device)
+        if out.dtype != torch.uint8 or out.numel() < n:
+            raise ValueError("out must be a uint8 device tensor with one byte per key")
         _check(fn(self._h, _dev_ptr(keys, "keys"), _dev_ptr(offsets, "offsets"), n, _dev_ptr(out, "out"),
                   _stream(stream)), name)
         return out
