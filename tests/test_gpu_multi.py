@@ -140,5 +140,7 @@ def test_table_set_rejects_oversized_batch(gpu):
     off = torch.tensor([0, 500, 1000, 1500, 2000], dtype=torch.int64, device=gpu)
     with pytest.raises(cpht.CphtError):
         m.insert(k, off)
+    with pytest.raises(ValueError):  # a result buffer shorter than the batch
+        m.insert(k[:1000], off.clamp(max=1000), out=torch.empty(999, dtype=torch.uint8, device=gpu))
     view = m.table(1)
     assert cpht.lib().cpht_destroy(view._h) == 7  # views cannot be destroyed on their own

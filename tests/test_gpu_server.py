@@ -204,3 +204,19 @@ def test_server_zero_copy_needs_pinned_buffers(gpu):
     srv.wait(srv.submit(pk, po, pout))
     assert (pout.numpy() == 0).all()  # an empty table finds nothing
     srv.stop()
+
+
+def test_server_replay_rejects_offsets_past_buffers(gpu):
+    t = _table(26)
+    srv = cpht.Server(t)
+    keys = synth.to_words(synth.feistel(W, 77, torch.arange(100, dtype=torch.int64)), W).pin_memory()
+    ops = torch.zeros(100, dtype=torch.uint8).pin_memory()
+    out = torch.zeros(100, dtype=torch.uint8).pin_memory()
+    arrival = np.zeros(2, dtype=np.uint64)
+    with pytest.raises(ValueError):  # the second request would read keys 100..149
+        srv.replay(arrival, np.array([0, 50, 150], dtype=np.uint64), keys, ops, out)
+    with pytest.raises(ValueError):  # one offset short
+        srv.replay(arrival, np.array([0, 50], dtype=np.uint64), keys, ops, out)
+    lat, _ = srv.replay(arrival, np.array([0, 50, 100], dtype=np.uint64), keys, ops, out)
+    srv.stop()
+    assert (lat > 0).all() and (out.numpy() == 0).all()
