@@ -25,6 +25,7 @@
 #include <mutex>
 #include <new>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "cpht.h"
@@ -180,26 +181,28 @@ bool adjacent(const Request& a, const Request& b, uint64_t key_bytes) {
          b.dops == a.dops + a.n && b.dout == a.dout + a.n;
 }
 
-// Device view of a pinned host range [h, h + bytes); nullptr unless both ends
-// lie in pinned host memory mapped for the device with the same offset
-// between host and device addresses.
-bool host_mapping(const void* p, intptr_t* delta) {
-  hipPointerAttribute_t a;
-  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
-    (void)hipGetLastError();  // an unknown (pageable) pointer leaves an error behind
-    return false;
-  }
-  if (a.type != hipMemoryTypeHost || !a.devicePointer || !a.hostPointer) return false;
-  *delta = static_cast<const char*>(a.devicePointer) - static_cast<const char*>(a.hostPointer);
-  return true;
-}
-
+// Device view of a pinned host range [h, h + bytes); nullptr unless h lies in
+// pinned host memory mapped for the device and the whole range lies inside
+// that one allocation (so the device never touches an unmapped address).
 template <class T>
 T* device_view(T* h, uint64_t bytes) {
-  const char* b = reinterpret_cast<const char*>(h);
-  intptr_t d0 = 0, d1 = 0;
-  if (!host_mapping(b, &d0) || !host_mapping(b + bytes - 1, &d1) || d0 != d1) return nullptr;
-  return reinterpret_cast<T*>(const_cast<char*>(b) + d0);
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, static_cast<const void*>(h)) != hipSuccess) {
+    (void)hipGetLastError();  // an unknown (pageable) pointer leaves an error behind
+    return nullptr;
+  }
+  if (a.type != hipMemoryTypeHost || !a.devicePointer || !a.hostPointer) return nullptr;
+  const intptr_t delta = static_cast<const char*>(a.devicePointer) - static_cast<const char*>(a.hostPointer);
+  char* d = reinterpret_cast<char*>(const_cast<typename std::remove_const<T>::type*>(h)) + delta;
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, d) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  const char* b = static_cast<const char*>(base);
+  if (d < b || d + bytes > b + size) return nullptr;
+  return reinterpret_cast<T*>(d);
 }
 
 void dispatcher(cpht_server* s) {
