@@ -62,12 +62,32 @@ def candidates(scheme: int, key_bits: int, log2_slots0: int, max_bucket_bytes: i
 
 
 def _random_keys(n: int, key_bits: int, gen: torch.Generator, device) -> torch.Tensor:
-    """n uniform keys of key_bits bits as the library's key words, drawn on `device`."""
-    hi = 1 << min(key_bits, 62)
-    k = torch.randint(0, hi, (n,), generator=gen, dtype=torch.int64, device=gen.device)
+    """n distinct keys of key_bits bits (n <= 2^key_bits) as the library's key
+    words, drawn on `device`: a random start and odd stride modulo 2^key_bits
+    (a bijection of the index), so a cuckoo build gets the distinct keys its
+    contract asks for; the table's own permutation spreads them over buckets."""
+    w = min(key_bits, 63)
+    mask = (1 << w) - 1
+    start = int(torch.randint(0, 1 << 62, (1,), generator=gen, device=gen.device).item()) & mask
+    stride = (int(torch.randint(0, 1 << 62, (1,), generator=gen, device=gen.device).item()) & mask) | 1
+    i = torch.arange(n, dtype=torch.int64, device=device)
+    k = (start + i * stride) & mask  # wraps mod 2^64 before the mask: still i -> k is a bijection mod 2^w
     if key_bits <= 32:
         return (k & 0xFFFFFFFF).to(torch.int32)
     return k
+
+
+def pick(entries: list[tuple[float | None, float, bool]], tie: float = 0.03) -> int:
+    """Index of the winner among (time or None if the candidate failed, bits
+    per slot, is the preferred variant): the failed are dropped, candidates
+    within `tie` of the fastest count as equally fast, and among those the
+    least memory wins, then the preferred one, then the faster."""
+    ok = [i for i, (ms, _, _) in enumerate(entries) if ms is not None]
+    if not ok:
+        raise RuntimeError("no candidate reaches the target load")
+    fastest = min(entries[i][0] for i in ok)
+    near = [i for i in ok if entries[i][0] <= fastest * (1 + tie)]
+    return min(near, key=lambda i: (entries[i][1], not entries[i][2], entries[i][0]))
 
 
 def _gen(device, seed: int) -> torch.Generator:
@@ -127,25 +147,23 @@ def tune(scheme: int, key_bits: int, log2_slots0: int, load: float, device="cuda
     share a kernel variant and a table set needs fewer launches)."""
     k = _key(scheme, key_bits, log2_slots0, load)
     if k not in _CACHE:
-        timed, tried = [], []
-        for c in candidates(scheme, key_bits, log2_slots0):
-            m = measure(c, load, device, reps)
-            tried.append({"bucket0": c.bucket0, "slot_bits0": c.slot_bits0, "slot_bits1": c.slot_bits1,
-                          "subtile": c.subtile, "ms": None if m is None else round(m["total_ms"], 4)})
-            if m is not None:
-                timed.append((m["total_ms"], c))
-        if not timed:
-            raise RuntimeError(f"no configuration reaches load {load} at 2^{log2_slots0} slots")
-        fastest = min(ms for ms, _ in timed)
-        near = [c for ms, c in timed if ms <= fastest * (1 + tie)]
+        cands, entries, tried = candidates(scheme, key_bits, log2_slots0), [], []
 
         def same(c):
             return prefer is not None and all(
                 getattr(c, f) == getattr(prefer, f) for f in ("bucket0", "slot_bits0", "slot_bits1", "subtile"))
 
-        best = min(near, key=lambda c: (_bits_per_slot(c), not same(c)))
-        best_ms = next(ms for ms, c in timed if c is best)
-        _CACHE[k] = {"config": best.as_dict(), "ms": best_ms, "tried": tried}
+        for c in cands:
+            m = measure(c, load, device, reps)
+            ms = None if m is None else m["total_ms"]
+            tried.append({"bucket0": c.bucket0, "slot_bits0": c.slot_bits0, "slot_bits1": c.slot_bits1,
+                          "subtile": c.subtile, "ms": None if ms is None else round(ms, 4)})
+            entries.append((ms, _bits_per_slot(c), same(c)))
+        try:
+            w = pick(entries, tie)
+        except RuntimeError:
+            raise RuntimeError(f"no configuration reaches load {load} at 2^{log2_slots0} slots") from None
+        _CACHE[k] = {"config": cands[w].as_dict(), "ms": entries[w][0], "tried": tried}
     c = Config()
     for name, v in _CACHE[k]["config"].items():
         setattr(c, name, v)
@@ -177,9 +195,9 @@ def tune_set(scheme: int, key_bits: int, log2_sizes: list[int], load: float, dev
     qo = torch.tensor([0] + list(torch.tensor(q_t).cumsum(0).tolist()), dtype=torch.int64, device=device)
     tid = torch.repeat_interleave(torch.arange(len(caps)), torch.tensor(q_t)).to(device)
     ntd = torch.tensor(n_t, dtype=torch.int64, device=device)
-    pick = ko[:-1][tid] + (torch.rand(tid.numel(), generator=gen, device=gen.device) * ntd[tid]).long()
+    hit_at = ko[:-1][tid] + (torch.rand(tid.numel(), generator=gen, device=gen.device) * ntd[tid]).long()
     hits = torch.rand(tid.numel(), generator=gen, device=gen.device) < 0.5
-    queries = torch.where(hits, keys[pick.clamp(max=keys.numel() - 1)],
+    queries = torch.where(hits, keys[hit_at.clamp(max=keys.numel() - 1)],
                           _random_keys(tid.numel(), key_bits, gen, device))
     out = torch.empty(keys.numel(), dtype=torch.uint8, device=device)
     found = torch.empty(queries.numel(), dtype=torch.uint8, device=device)
@@ -213,12 +231,11 @@ def tune_set(scheme: int, key_bits: int, log2_sizes: list[int], load: float, dev
         rows.append({"bucket0": c.bucket0, "slot_bits0": c.slot_bits0, "slot_bits1": c.slot_bits1,
                      "subtile": c.subtile, "ms": round(min(times), 3), "full": nfull, "ok": ok,
                      "bits_per_slot": _bits_per_slot(c)})
-    good = [r for r in rows if r["ok"]]
-    if not good:
-        raise RuntimeError("no variant reaches the target load for the set")
-    fastest = min(r["ms"] for r in good)
-    near = [r for r in good if r["ms"] <= fastest * (1 + tie)]
-    best = min(near, key=lambda r: (r["bits_per_slot"], r["ms"]))
+    try:
+        w = pick([(r["ms"] if r["ok"] else None, r["bits_per_slot"], False) for r in rows], tie)
+    except RuntimeError:
+        raise RuntimeError("no variant reaches the target load for the set") from None
+    best = rows[w]
     return {k: best[k] for k in ("bucket0", "slot_bits0", "slot_bits1", "subtile")}, rows
 
 
@@ -231,4 +248,4 @@ def report(scheme: int, key_bits: int, log2_slots0: int, load: float) -> dict | 
     return _CACHE.get(_key(scheme, key_bits, log2_slots0, load))
 
 
-__all__ = ["candidates", "measure", "tune", "tune_set", "report", "load_cache", "save_cache", "CUCKOO", "ICEBERG"]
+__all__ = ["candidates", "measure", "pick", "tune", "tune_set", "report", "load_cache", "save_cache", "CUCKOO", "ICEBERG"]
