@@ -268,3 +268,82 @@ def test_c4_many_tables_full_size(gpu):
         g.replay()
         torch.cuda.synchronize()
         check_answers(f"replay {r}")
+
+
+@pytest.mark.parametrize("scheme", ["cuckoo", "iceberg"])
+def test_delete_full_size(gpu, scheme):
+    """The delete workload at full size: a table at load 0.9 (2^27 slots
+    cuckoo, 2^27 + 2^24 iceberg 16/32), one batch of 2^26 deletes, half of
+    them distinct stored keys and half never inserted.  Per key: 1 exactly
+    for the stored ones; afterwards the deleted keys are not found, every
+    other stored key is, and the count dropped by the deleted keys."""
+    w, L, nd = 37, 27, 1 << 26
+    if scheme == "cuckoo":
+        t = cpht.Table(scheme=cpht.CUCKOO, key_bits=w, log2_slots0=L, bucket0=32, slot_bits0=32, seed=83)
+    else:
+        t = cpht.Table(scheme=cpht.ICEBERG, key_bits=w, log2_slots0=L, log2_slots1=L - 3, bucket0=32, bucket1=16,
+                       slot_bits0=16, slot_bits1=32, seed=83)
+    cap = t.count()[1]
+    n = int(0.9 * cap)
+    keys = synth.distinct_keys(w, SEED + 5, 0, n, device=gpu)
+    assert _count(t.insert(keys) != cpht.PUT) == 0
+    perm = synth.permutation(77, n, device=gpu)
+    gone = perm[: nd // 2]
+    q = torch.cat([keys[gone], synth.distinct_keys(w, SEED + 5, n, nd // 2, device=gpu)])
+    order = synth.permutation(78, nd, device=gpu)
+    q = q[order]
+    truth = (order < nd // 2).to(torch.uint8)  # position i holds a stored key iff it came from the first half
+    bad = _diff(t.delete(q), truth)
+    assert bad == 0, f"{bad} delete answers differ"
+    assert t.count()[0] == n - nd // 2
+    deleted = torch.zeros(n, dtype=torch.bool, device=gpu)
+    deleted[gone] = True
+    bad = _diff(t.find(keys), (~deleted).to(torch.uint8))
+    assert bad == 0, f"{bad} lookups after the deletes differ"
+
+
+def test_level3_full_size(gpu):
+    """The third level at the benchmark's shape: 2^27 + 2^24 slots (16/32),
+    2^17 lists and a pool of 2^20 slabs, distinct keys to load 1.0 of the
+    bucket levels in one batch.  No FULL; the count equals the keys; every
+    key is found and 2^24 never-inserted keys are not; the table checker
+    walks every list of the images."""
+    w, L = 37, 27
+    t = cpht.Table(scheme=cpht.ICEBERG, key_bits=w, log2_slots0=L, log2_slots1=L - 3, bucket0=32, bucket1=16,
+                   slot_bits0=16, slot_bits1=32, log2_lists=17, pool_slabs=1 << 20, seed=84)
+    cap = t.count()[1]
+    keys = synth.distinct_keys(w, SEED + 13, 0, cap, device=gpu)
+    out = t.insert(keys)
+    n_full = _count(out == cpht.FULL)
+    assert n_full == 0
+    assert _count(out != cpht.PUT) == 0
+    assert t.count()[0] == cap
+    used = t.level3_used()
+    assert 0 < used < (1 << 20)
+    missed = _count(t.find(keys) != 1)
+    assert missed == 0
+    false_hits = _count(t.find(synth.distinct_keys(w, SEED + 13, 1 << 36, 1 << 24, device=gpu)) != 0)
+    assert false_hits == 0
+    ok, msg, dec = oracle.check_images(oracle_cfg(t), *[t.export(x) for x in range(t.nimages)])
+    assert ok, msg
+    assert dec.size == cap
+
+
+def test_map_full_size(gpu):
+    """The map at the benchmark's shape: 2^27 + 2^24 slots (16/32) with 8-byte
+    values, distinct keys to load 0.9 with value mix64(key), then 2^26 lookups
+    (half hits): found flags exact, every value found is its key's."""
+    w, L = 37, 27
+    t = cpht.Table(scheme=cpht.ICEBERG, key_bits=w, log2_slots0=L, log2_slots1=L - 3, bucket0=32, bucket1=16,
+                   slot_bits0=16, slot_bits1=32, value_bytes=8, seed=85)
+    cap = t.count()[1]
+    n = int(0.9 * cap)
+    keys = synth.distinct_keys(w, SEED, 0, n, device=gpu)  # phi(i < n): the keys _queries draws hits from
+    assert _count(t.insert_values(keys, synth.mix64_t(keys)) != cpht.PUT) == 0
+    q, truth = _queries(w, n, 1 << 26, 9, gpu)
+    found, vals = t.find_values(q)
+    bad = _diff(found, truth)
+    assert bad == 0, f"{bad} found flags differ"
+    hit = truth.bool()
+    wrong = _diff(vals[hit], synth.mix64_t(q[hit]))
+    assert wrong == 0, f"{wrong} values differ"
