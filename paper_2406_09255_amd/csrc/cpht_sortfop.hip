@@ -15,7 +15,10 @@
 //      the cuckoo put kernel;
 //   5. every input position gets its answer: FOUND for keys already stored,
 //      and for a missing key the put's PUT or FULL at its first occurrence and
-//      FOUND (or FULL) at the later ones.
+//      FOUND (or FULL) at the later ones.  The answers are produced in sorted
+//      order; rather than scattering single bytes over the whole output, they
+//      are packed with their positions, partitioned by the positions' high
+//      bits (one more radix round) and written one output window at a time.
 //
 // Counts that only the device knows (distinct keys, missing keys) stay on the
 // device: the lookup and put run as persistent launches over chunk lists that
@@ -213,6 +216,7 @@ __global__ __launch_bounds__(TPB, 3) void sort_scatter(const K* __restrict__ kin
   }
   __syncthreads();
   for (uint32_t p = threadIdx.x; p < tile_n; p += TPB) kout[(uint64_t)obase[sdig[p]] + p] = stage[p];
+  if (iout == nullptr) return;  // keys only (uniform across the block)
   __syncthreads();
   // input positions, through the same buffer
   uint32_t* sidx = reinterpret_cast<uint32_t*>(stage);
@@ -402,6 +406,40 @@ __global__ __launch_bounds__(TPB) void final_answers(const uint32_t* __restrict_
   }
 }
 
+// The same answers as final_answers, packed with their input position for a
+// partition by position: packed[i] = pos[i] << 2 | answer (n <= 2^30).
+__global__ __launch_bounds__(TPB) void pack_answers(const uint32_t* __restrict__ uniq,
+                                                    const uint32_t* __restrict__ pos,
+                                                    const uint8_t* __restrict__ uo, uint64_t n,
+                                                    uint32_t* __restrict__ packed) {
+  for (uint64_t i = (uint64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (uint64_t)gridDim.x * TPB) {
+    const uint32_t u = uniq[i];
+    const uint8_t o = uo[u];
+    const bool head = i == 0 || uniq[i - 1] != u;
+    const uint32_t a = head ? o : (o == R_PUT ? (uint32_t)R_FOUND : o);
+    packed[i] = (pos[i] << 2) | a;
+  }
+}
+
+// Answers partitioned by the high bits of their position: tile t of the
+// partition writes bytes that all fall in a few windows of the output, and
+// consecutive tiles go to the same XCD, so each window's lines fill up in one
+// L2 before they are written back.
+__global__ __launch_bounds__(TPB) void write_answers(const uint32_t* __restrict__ parts, uint64_t n,
+                                                     uint32_t ntiles, uint8_t* __restrict__ out) {
+  const uint64_t tile = tile_of_block(ntiles);
+  if (tile >= ntiles) return;
+  const uint64_t base = tile * TILE + threadIdx.x;
+#pragma unroll 4
+  for (int r = 0; r < IPT; ++r) {
+    const uint64_t j = base + (uint64_t)r * TPB;
+    if (j < n) {
+      const uint32_t w = parts[j];
+      out[w >> 2] = (uint8_t)(w & 3u);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Workspace layout
 // ---------------------------------------------------------------------------
@@ -524,8 +562,28 @@ hipError_t run(const TableK& T, const CkVariant* v, int key_bits, const K* keys,
   const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n + TPB - 1) / TPB, 65536));
   hipLaunchKernelGGL(put_answers, dim3(grid), dim3(TPB), 0, s, (const uint32_t*)pidx, (const uint8_t*)pout,
                      (const uint64_t*)(misc + 1), uo);
-  hipLaunchKernelGGL(final_answers, dim3(grid), dim3(TPB), 0, s, (const uint32_t*)uniq, pos,
-                     (const uint8_t*)uo, n, out);
+  if (n > (1ull << 30)) {  // positions too wide to pack with a 2-bit answer: scatter directly
+    hipLaunchKernelGGL(final_answers, dim3(grid), dim3(TPB), 0, s, (const uint32_t*)uniq, pos,
+                       (const uint8_t*)uo, n, out);
+    return hipGetLastError();
+  }
+  // pack (position, answer), partition by the top 8 bits of the packed word
+  // (one stable radix round), then write each partition's bytes together
+  uint32_t* packed = reinterpret_cast<uint32_t*>(const_cast<K*>(sorted));  // free since step 2
+  uint32_t* parts = reinterpret_cast<uint32_t*>(U);                        // free since step 4
+  hipLaunchKernelGGL(pack_answers, dim3(grid), dim3(TPB), 0, s, (const uint32_t*)uniq, pos, (const uint8_t*)uo, n,
+                     packed);
+  uint32_t pb = 2;  // bits of the packed word: positions < n, shifted by 2
+  while ((1ull << pb) < 4 * n) ++pb;
+  const uint32_t pshift = pb > 8 ? pb - 8 : 0;
+  hipLaunchKernelGGL(sort_hist<uint32_t>, dim3(tile_grid(ntiles)), dim3(TPB), 0, s, (const uint32_t*)packed, n,
+                     pshift, counts, (uint32_t)ntiles);
+  run_scan(CountsScan{counts, (uint64_t)RADIX * ntiles}, (uint64_t)RADIX * ntiles, psum, nullptr, s);
+  hipLaunchKernelGGL(sort_scatter<uint32_t>, dim3(tile_grid(ntiles)), dim3(TPB), 0, s, (const uint32_t*)packed,
+                     (const uint32_t*)nullptr, parts, (uint32_t*)nullptr, n, pshift, (const uint32_t*)counts,
+                     (uint32_t)ntiles);
+  hipLaunchKernelGGL(write_answers, dim3(tile_grid(ntiles)), dim3(TPB), 0, s, (const uint32_t*)parts, n,
+                     (uint32_t)ntiles, out);
   return hipGetLastError();
 }
 
