@@ -340,8 +340,10 @@ cpht_status_t cpht_multi_error(cpht_multi_t m, uint32_t* flags);
  * tensor after pin_memory()), the mixed kernel reads the keys and opcodes and
  * writes the results in place, and a launch covers a run of queued requests
  * that lie back to back in all three buffers (up to max_batch_keys keys).
- * The table must outlive the server.  The server keeps a small record (about
- * 72 bytes) per ticket until it stops.  After a device error every pending and
+ * The server runs set operations (cpht_mixed): on a map table the values are
+ * neither written nor returned.  The table must outlive the server, and no
+ * other call may clear or import into it while the server runs.  The server
+ * keeps a small record (about 72 bytes) per ticket until it stops.  After a device error every pending and
  * later request completes at once (results undefined) and submit, poll and
  * wait return CPHT_E_DEVICE. */
 typedef struct cpht_server* cpht_server_t;
