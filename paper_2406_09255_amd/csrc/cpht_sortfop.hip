@@ -160,12 +160,21 @@ __global__ __launch_bounds__(TPB, 3) void sort_scatter(const K* __restrict__ kin
   const uint64_t seg = tbase + (uint64_t)wv * SEG;
   const uint64_t below = (1ull << lane) - 1ull;
   K key[IPT];
+  uint32_t src[IPT];  // input position carried with each key (absent in keys-only rounds)
   uint32_t pos[IPT];  // rank among the wave's keys of the same digit, then slot in the tile
+  // all of the tile's loads first, so they are in flight together (the
+  // ranking below is serialised by its shared-memory counters)
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    const uint64_t i = seg + (uint64_t)r * 64 + lane;
+    key[r] = i < n ? kin[i] : (K)0;
+    src[r] = iin && i < n ? iin[i] : (uint32_t)i;
+  }
 #pragma unroll
   for (int r = 0; r < IPT; ++r) {
     const uint64_t i = seg + (uint64_t)r * 64 + lane;
     const bool valid = i < n;
-    const K k = valid ? kin[i] : (K)0;
+    const K k = key[r];
     const uint32_t d = (uint32_t)(k >> shift) & (RADIX - 1u);
     const uint64_t vm = __ballot(valid);
     const uint64_t peers = same_digit(d, vm);
@@ -176,7 +185,6 @@ __global__ __launch_bounds__(TPB, 3) void sort_scatter(const K* __restrict__ kin
     const uint32_t b = valid ? *ctr : 0u;
     if (valid && (peers & below) == 0ull) *ctr = b + (uint32_t)__popcll(peers);
     pos[r] = b + (uint32_t)__popcll(peers & below);
-    key[r] = k;
   }
   __syncthreads();
 
@@ -223,7 +231,7 @@ __global__ __launch_bounds__(TPB, 3) void sort_scatter(const K* __restrict__ kin
 #pragma unroll
   for (int r = 0; r < IPT; ++r) {
     const uint64_t i = seg + (uint64_t)r * 64 + lane;
-    if (i < n) sidx[pos[r]] = iin ? iin[i] : (uint32_t)i;
+    if (i < n) sidx[pos[r]] = src[r];
   }
   __syncthreads();
   for (uint32_t p = threadIdx.x; p < tile_n; p += TPB) iout[(uint64_t)obase[sdig[p]] + p] = sidx[p];
