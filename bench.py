@@ -933,6 +933,20 @@ def progress(name: str):
     print(f"[bench] {name} done at {time.perf_counter() - _T0:.1f} s", file=sys.stderr, flush=True)
 
 
+def run_section(res: dict, name: str, fn):
+    """res[name] = fn(); a section that raises is reported in its place (and
+    its traceback on stderr) so that the headline and the other sections
+    still make the JSON line."""
+    try:
+        res[name] = fn()
+    except Exception as e:  # noqa: BLE001 - reported, not hidden
+        import traceback
+
+        traceback.print_exc()
+        res[name] = {"error": f"{type(e).__name__}: {e}"}
+    progress(name)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -1100,12 +1114,10 @@ def main():
         progress("plain")
 
     if not args.no_plain and not args.no_equal:
-        res["equal_memory"] = equal_memory(torch, cpht, keys, queries, n_ins)
-        progress("equal_memory")
+        run_section(res, "equal_memory", lambda: equal_memory(torch, cpht, keys, queries, n_ins))
 
     if not args.no_window:
-        res["marginal_window"] = marginal_window(torch, cpht, keys, n_ins)
-        progress("marginal_window")
+        run_section(res, "marginal_window", lambda: marginal_window(torch, cpht, keys, n_ins))
 
     if not args.no_sweep:
         loads = (0.5, 0.7, 0.8, 0.9, 0.95)
@@ -1137,46 +1149,35 @@ def main():
         progress("sweep")
 
     if not args.no_small:
-        res["small_cuckoo"] = small_cuckoo(torch, cpht, synth, dev)
-        progress("small_cuckoo")
+        run_section(res, "small_cuckoo", lambda: small_cuckoo(torch, cpht, synth, dev))
 
     if not args.no_iceberg:
-        res["iceberg_static"] = iceberg_static(torch, cpht, synth, dev)
-        progress("iceberg_static")
-        res["iceberg_mixed"] = iceberg_mixed(torch, cpht, synth, dev)
-        progress("iceberg_mixed")
-        res["iceberg_zipf"] = iceberg_zipf(torch, cpht, synth, dev)
-        progress("iceberg_zipf")
+        run_section(res, "iceberg_static", lambda: iceberg_static(torch, cpht, synth, dev))
+        run_section(res, "iceberg_mixed", lambda: iceberg_mixed(torch, cpht, synth, dev))
+        run_section(res, "iceberg_zipf", lambda: iceberg_zipf(torch, cpht, synth, dev))
 
     if not args.no_fop:
-        res["find_or_put"] = find_or_put(torch, cpht, synth, dev)
-        progress("find_or_put")
+        run_section(res, "find_or_put", lambda: find_or_put(torch, cpht, synth, dev))
 
     if not args.no_delete:
-        res["delete"] = deletes(torch, cpht, synth, dev)
-        progress("delete")
+        run_section(res, "delete", lambda: deletes(torch, cpht, synth, dev))
 
     if not args.no_level3:
-        res["level3"] = level3(torch, cpht, synth, dev)
-        progress("level3")
+        run_section(res, "level3", lambda: level3(torch, cpht, synth, dev))
 
     if not args.no_map:
-        res["map"] = kv_map(torch, cpht, synth, dev)
-        progress("map")
+        run_section(res, "map", lambda: kv_map(torch, cpht, synth, dev))
 
     if not args.no_many:
-        res["many_tables"] = many_tables(torch, cpht, synth, dev)
-        progress("many_tables")
+        run_section(res, "many_tables", lambda: many_tables(torch, cpht, synth, dev))
 
     if not args.no_serving:
-        res["serving"] = serving(torch, cpht, synth, dev)
-        progress("serving")
+        run_section(res, "serving", lambda: serving(torch, cpht, synth, dev))
 
     if not args.no_ceilings:
-        res["ceilings"] = ceilings(torch, cpht, dev, res)
-        progress("ceilings")
-        c = res["ceilings"]["table_size"]
-        if res["roofline"]["kernel"] == "cuckoo_put":
+        run_section(res, "ceilings", lambda: ceilings(torch, cpht, dev, res))
+        c = res["ceilings"].get("table_size")
+        if c is not None and res["roofline"]["kernel"] == "cuckoo_put":
             # one CAS per put round: the device's random line-read-then-CAS rate bounds the kernel
             res["roofline"]["atomic_ceiling"] = {
                 "what": "measured random 128-B line read + 32-bit CAS into it, table-sized buffer",
@@ -1185,8 +1186,7 @@ def main():
                 "frac": res["ceilings"]["put_vs_line_read_then_cas"]}
 
     if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline()
-        progress("cpu_baseline")
+        run_section(res, "cpu_baseline", cpu_baseline)
     print(json.dumps(res))
 
 

@@ -53,3 +53,22 @@ def test_iceberg_overflow_rates_match_the_oracle():
     _, lfind = t.find(q, lines=True)
     assert abs((lput.mean() - 1) / 2 - bench.ICE_L2["put"]) < 0.01
     assert abs((lfind.mean() - 1) / 2 - bench.ICE_L2["find"]) < 0.02
+
+
+def test_a_failing_section_is_reported_not_fatal(capsys):
+    res = {}
+    bench.run_section(res, "good", lambda: {"x": 1})
+
+    def bad():
+        raise RuntimeError("boom")
+
+    bench.run_section(res, "bad", bad)
+    assert res["good"] == {"x": 1}
+    assert res["bad"] == {"error": "RuntimeError: boom"}
+    err = capsys.readouterr().err
+    assert "boom" in err and "[bench] bad done" in err
+
+
+def test_iceberg_traffic_is_tied_to_iceberg_sources():
+    assert bench.csrc_sha(bench.ICE_SOURCES) != bench.csrc_sha()
+    assert set(bench.ICE_TRAFFIC) == {"src_sha", "insert_16_32", "find_16_32", "insert_64_64", "find_64_64"}
