@@ -421,6 +421,12 @@ class Table:
         _check(lib().cpht_level_bytes(self._h, level, ctypes.byref(b)), "cpht_level_bytes")
         return b.value
 
+    def level_ptr(self, level: int) -> int:
+        """Device address of image `level` (for callers that read it themselves)."""
+        p = _VP()
+        _check(lib().cpht_level_ptr(self._h, level, ctypes.byref(p)), "cpht_level_ptr")
+        return p.value or 0
+
     def export(self, level: int):
         """Raw slot image of a level in host memory (numpy uint8)."""
         import numpy as np  # host staging buffer only
