@@ -31,6 +31,11 @@
  *   - The library owns table memory (device memory of the device current at
  *     cpht_create).  Batch calls allocate nothing.
  *   - n = 0 is valid for every batch call and launches nothing.
+ *   - Batch calls, cpht_clear, cpht_sorted_fop and the table-set calls launch
+ *     kernels only (no memset or copy nodes), so they can be captured in a
+ *     HIP graph.  A captured call keeps the arguments of capture time,
+ *     including the permutation constants: a replay uses the seed that was
+ *     current when it was captured, whatever an eager cpht_clear set since.
  */
 #ifndef CPHT_H
 #define CPHT_H
