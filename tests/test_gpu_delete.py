@@ -126,3 +126,25 @@ def test_delete_edge_cases(gpu):
     assert t.count()[0] == 0 and _tombs(t) == 1000
     t.clear()
     assert _tombs(t) == 0 and t.count()[0] == 0
+
+
+def test_cuckoo_reinsert_deleted_keys(gpu):
+    """A deleted key is absent, so the cuckoo put takes it again: it lands in
+    an empty slot (tombstones are not reused by the first-empty claim, though
+    an eviction may overwrite one).  Key set, lookups and count follow the
+    oracle; tombstones never exceed the deletes."""
+    w = 32
+    t = cpht.Table(scheme=cpht.CUCKOO, key_bits=w, log2_slots0=13, bucket0=16, slot_bits0=32, seed=0xD7)
+    o = oracle_table(t)
+    kh = host_u64(synth.distinct_keys(w, KEY_SEED + 9, 0, 5000))
+    assert (t.insert(_dev(kh, w, gpu)) == cpht.PUT).all() and (o.insert(kh) == oracle.PUT).all()
+    gone = kh[::5]
+    assert (t.delete(_dev(gone, w, gpu)) == 1).all() and (o.delete(gone) == 1).all()
+    assert int(t.find(_dev(gone, w, gpu)).sum().item()) == 0
+    got = t.insert(_dev(gone, w, gpu)).cpu().numpy()
+    assert (got == cpht.PUT).all() and (o.insert(gone) == oracle.PUT).all()
+    assert np.array_equal(check_table(t), np.sort(kh))
+    assert t.count()[0] == kh.size == o.occupied()
+    assert 0 < _tombs(t) <= gone.size
+    q = np.concatenate([kh, host_u64(synth.distinct_keys(w, KEY_SEED + 9, 5000, 2000))])
+    assert np.array_equal(t.find(_dev(q, w, gpu)).cpu().numpy(), o.find(q))
