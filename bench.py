@@ -422,6 +422,31 @@ def cpu_baseline(log2_slots: int = 26):
     t2 = time.perf_counter()
     assert (out == oracle.PUT).all()
     del torch
+    # context beside the sample: the small cuckoo shape whole, and a 1/16 sample
+    # of the iceberg shape (compact 16/32, load 0.9, finds at 50 % hit)
+    ks = synth.distinct_keys(32, KEY_SEED + 21, 0, 104857).numpy().astype(np.uint64)
+    qs = synth.find_queries(32, KEY_SEED + 21, 104857, 100000, 0.5, Q_SEED + 21).numpy().astype(np.uint64)
+    ts = oracle.Table(oracle.CUCKOO, 32, 17, 32, 32, seed=1)
+    a = time.perf_counter()
+    ts.insert(ks)
+    b = time.perf_counter()
+    ts.find(qs)
+    c = time.perf_counter()
+    small = {"insert_us": round((b - a) * 1e6, 1), "find_us": round((c - b) * 1e6, 1),
+             "shape": "cuckoo 2^17 slots, 32 x 32-bit buckets, 32-bit keys: 104857 inserts, 10^5 finds"}
+    ni, nqi = int(LOAD * ((1 << 23) + (1 << 20))), 1 << 22
+    ki = synth.distinct_keys(33, KEY_SEED + 22, 0, ni).numpy().astype(np.uint64)
+    qi = synth.find_queries(33, KEY_SEED + 22, ni, nqi, 0.5, Q_SEED + 22).numpy().astype(np.uint64)
+    ti = oracle.Table(oracle.ICEBERG, 33, 23, 32, 16, log2_slots1=20, B1=16, s1=32, seed=5)
+    a = time.perf_counter()
+    ti.insert(ki)
+    b = time.perf_counter()
+    ti.find(qi)
+    c = time.perf_counter()
+    ice = {"insert_mops": round(ni / (b - a) / 1e6, 3), "find_mops": round(nqi / (c - b) / 1e6, 3),
+           "shape": f"iceberg 2^23 + 2^20 slots (16/32-bit, 33-bit keys: at 1/16 of the iceberg benchmark's slots a "
+                    f"16-bit primary slot holds 33-bit keys' remainders), "
+                    f"{ni} inserts to load {LOAD}, {nqi} finds at 50% hit"}
     return {
         "value": round((n + nq) / (t2 - t0) / 1e6, 3),
         "unit": "Mops/s",
@@ -436,6 +461,8 @@ def cpu_baseline(log2_slots: int = 26):
         "hit_fraction": round(float(f.mean()), 4),
         "host_threads_available": os.cpu_count(),
         "host_cpu": _host_cpu(),
+        "small_cuckoo": small,
+        "iceberg_sample": ice,
     }
 
 
