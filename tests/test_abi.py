@@ -68,3 +68,18 @@ def test_null_arguments():
     assert L.cpht_create(None, None) == 1
     assert L.cpht_destroy(None) == 1
     assert L.cpht_find(None, None, 0, None, None) == 1
+
+
+def test_every_entry_point_rejects_null_arguments():
+    """Every call returning a status answers CPHT_E_ARG to null handles and
+    pointers (zero sizes), before touching any device."""
+    L = cpht.lib()
+    ints = (ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int)
+    checked = 0
+    for name, (res, args) in sorted(cpht._SIGNATURES.items()):
+        if res is not cpht._I32 or name == "cpht_variant_info":  # variant_info returns a count
+            continue
+        vals = [0 if a in ints else None for a in args]
+        assert getattr(L, name)(*vals) == 1, name
+        checked += 1
+    assert checked >= 40
