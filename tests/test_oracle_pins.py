@@ -261,6 +261,112 @@ def test_iceberg_brute_force_tiny_domain():
             assert _buckets_full_without(img0 if lvl == 0 else img1, 32, B, b, e)
 
 
+# ---------------------------------------------------------------------------
+# the Theorem 1 (e) checker for FULL answers
+# ---------------------------------------------------------------------------
+
+# a tiny iceberg shape: 4 primary buckets of 4 x 32-bit slots (2 address
+# bits, 8 payload bits), 2 secondary buckets of 2 x 32-bit slots (1 address
+# bit, 9 payload bits, 1 tag bit), 10-bit keys
+_TINY = dict(w=10, L0=4, B0=4, L1=2, B1=2, seed=31)
+
+
+def _tiny_iceberg(seed):
+    c = _TINY
+    return oracle.Table(oracle.ICEBERG, c["w"], c["L0"], c["B0"], 32, log2_slots1=c["L1"], B1=c["B1"], s1=32,
+                        seed=seed)
+
+
+def _words(img):
+    return img.view(np.uint32)
+
+
+def _places(k, seed):
+    """(level, first word, slots, stored form) of key k's three buckets,
+    computed from the permutation and the documented slot layout
+    (occupancy bit 31 | tag << payload bits | payload), not from the
+    oracle's table code."""
+    c = _TINY
+    out = []
+    for i, (lvl, L, B, tag) in enumerate(((0, c["L0"], c["B0"], 0), (1, c["L1"], c["B1"], 0),
+                                         (1, c["L1"], c["B1"], 1))):
+        nb = L - int(np.log2(B))
+        a, r = oracle.split(c["w"], nb, seed, i, [k])
+        p = c["w"] - nb
+        out.append((lvl, int(a[0]) * B, B, (1 << 31) | (tag << p) | int(r[0])))
+    return out
+
+
+def _full_verdict_brute(imgs, k, seed):
+    """Theorem 1 (e) for key k straight from the images: its primary bucket
+    and both secondary buckets hold no EMPTY slot and not its stored form."""
+    for lvl, at, B, e in _places(k, seed):
+        words = _words(imgs[lvl])[at:at + B]
+        if (words == 0).any() or (words == e).any():
+            return False
+    return True
+
+
+@pytest.mark.parametrize("fill", [6, 12, 17, 20, 1 << 10])
+def test_check_full_equals_brute_force_over_the_domain(fill):
+    """For every key of the 2^10 domain, or_check_full accepts the key as a
+    legitimate FULL answer exactly when the raw images say its three buckets
+    are full without it; at several fills, so both full and non-full buckets,
+    stored and absent keys occur."""
+    seed = _TINY["seed"] + fill
+    t = _tiny_iceberg(seed)
+    keys = _rng(fill).permutation(1 << _TINY["w"]).astype(np.uint64)[:fill]
+    out = t.insert(keys)
+    imgs = [t.export(0), t.export(1)]
+    accepted = 0
+    for k in range(1 << _TINY["w"]):
+        want = _full_verdict_brute(imgs, k, seed)
+        got, msg = oracle.check_full(t.cfg, imgs[0], imgs[1], [k])
+        assert got == want, f"fill {fill}, key {k}: checker says {got} ({msg}), images say {want}"
+        accepted += got
+    if fill == 1 << 10:  # every slot is taken: exactly the keys answered FULL are accepted
+        assert accepted == int((out == oracle.FULL).sum()) == (1 << 10) - 20
+    elif fill < 16:  # some primary bucket still has room: keys aimed there are rejected
+        assert accepted < (1 << 10) - fill
+
+
+def test_check_full_rejects_planted_violations():
+    """On the whole-domain image (every slot full), for FULL keys: the
+    checker accepts the oracle's own FULL answers and rejects each planted
+    violation of Theorem 1 (e): the key stored in its primary bucket, in its
+    first secondary bucket (tag 0) or in its second (tag 1); an EMPTY slot in
+    any of the three buckets.  A stored form with the other secondary's tag
+    is some other key, not a violation."""
+    seed = _TINY["seed"]
+    t = _tiny_iceberg(seed)
+    keys = _rng(12).permutation(1 << _TINY["w"]).astype(np.uint64)
+    out = t.insert(keys)
+    full = keys[out == oracle.FULL]
+    img0, img1 = t.export(0), t.export(1)
+    ok, msg = oracle.check_full(t.cfg, img0, img1, full)
+    assert ok, msg
+    ok, _ = oracle.check_full(t.cfg, img0, img1, keys[out == oracle.PUT][:1])
+    assert not ok  # a stored key is no FULL answer
+    for k in full[:25]:
+        k = int(k)
+        places = _places(k, seed)
+        for which, (lvl, at, B, e) in enumerate(places):
+            for plant in ("store", "empty"):
+                imgs = [img0.copy(), img1.copy()]
+                words = _words(imgs[lvl])
+                words[at + (k % B)] = e if plant == "store" else 0
+                ok, msg = oracle.check_full(t.cfg, imgs[0], imgs[1], [k])
+                assert not ok, f"key {k}: planted {plant} in bucket {which} accepted"
+        # the second secondary bucket holding the key's payload under tag 0
+        # (the first secondary's tag) stores another key: still a valid FULL
+        lvl, at, B, e = places[2]
+        p = _TINY["w"] - (_TINY["L1"] - 1)
+        imgs = [img0.copy(), img1.copy()]
+        _words(imgs[1])[at] = e & ~np.uint64(1 << p)
+        ok, msg = oracle.check_full(t.cfg, imgs[0], imgs[1], [k])
+        assert ok, f"key {k}: the other tag's form was taken for the key: {msg}"
+
+
 def test_cuckoo_brute_force_tiny_domain():
     w = 10
     t = oracle.Table(oracle.CUCKOO, w, 5, 4, 32, seed=22, C=64)
