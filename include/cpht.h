@@ -55,7 +55,7 @@ typedef enum {
     CPHT_E_UNSUPPORTED = 3,  /* configuration not representable (e.g. remainder + tag + 1 > slot bits) */
     CPHT_E_KEYRANGE = 4,     /* reserved */
     CPHT_E_DEVICE = 5,       /* HIP runtime error */
-    CPHT_E_BUSY = 6,         /* reserved */
+    CPHT_E_BUSY = 6,         /* a serving loop's queue is full (cpht_server_submit) */
     CPHT_E_STATE = 7         /* operation not valid for this table (e.g. mixed batch on cuckoo) */
 } cpht_status_t;
 
@@ -138,7 +138,9 @@ cpht_status_t cpht_destroy(cpht_table_t t);
 cpht_status_t cpht_get_config(cpht_table_t t, cpht_config_t* cfg);
 
 /* Empty the table and re-derive the permutations from `seed` (stream-ordered;
- * uses a fill kernel, no memset node). */
+ * uses a fill kernel, no memset node).  On a table-set view the set's own
+ * launches use the new permutations from then on as well: a kernel on the
+ * same stream rewrites the set's device copy of the table's description. */
 cpht_status_t cpht_clear(cpht_table_t t, uint64_t seed, void* stream);
 
 /* Insert a batch.
@@ -348,7 +350,10 @@ cpht_status_t cpht_multi_error(cpht_multi_t m, uint32_t* flags);
  * The server runs set operations (cpht_mixed): on a map table the values are
  * neither written nor returned.  The table must outlive the server, and no
  * other call may clear or import into it while the server runs.  The server
- * keeps a small record (about 72 bytes) per ticket until it stops.  After a device error every pending and
+ * keeps a record (about 80 bytes) per ticket until the request has completed
+ * and either its ticket was waited on (or polled as done) or 2^20 later
+ * tickets exist; poll and wait return CPHT_E_ARG for a ticket whose record is
+ * gone.  After a device error every pending and
  * later request completes at once (results undefined) and submit, poll and
  * wait return CPHT_E_DEVICE. */
 typedef struct cpht_server* cpht_server_t;
@@ -407,7 +412,13 @@ cpht_status_t cpht_server_replay(cpht_server_t s, uint64_t n_requests, const uin
  * CAS kinds modify; d_sink: one device word the kernels may write.
  *   kind 0: random 128-byte line reads, 8 lanes x 16 bytes per line;
  *   kind 1: random 32-bit CAS (expected 0);
- *   kind 2: a random line read followed by a CAS into that line.
+ *   kind 2: a random line read followed by a CAS into that line;
+ *   kind 3: random 64-bit CAS (expected 0) on 8-byte words;
+ *   kind 4: the quotienting split alone (Sec. 2.4): d_buf holds uint64 keys,
+ *           read in order (wrapping round), each split under three
+ *           permutations of 37-bit keys into a 22-bit address and a stored
+ *           form, as the benchmark table does; nothing is written but d_sink
+ *           (practically never).  One operation = one key's three splits.
  * `ops` is rounded up to a multiple of 16384; *ops_done receives the count
  * actually issued.  Asynchronous on `stream`. */
 cpht_status_t cpht_probe(uint32_t kind, void* d_buf, uint64_t bytes, uint64_t ops, uint64_t seed, uint32_t* d_sink,

@@ -170,7 +170,7 @@ def variants(scheme: int) -> list[dict]:
     return out
 
 
-PROBE_LINES, PROBE_CAS, PROBE_LINE_CAS = 0, 1, 2
+PROBE_LINES, PROBE_CAS, PROBE_LINE_CAS, PROBE_CAS64, PROBE_SPLIT = 0, 1, 2, 3, 4
 
 
 def probe(kind: int, buf: torch.Tensor, ops: int, seed: int, sink: torch.Tensor, stream=None) -> int:

@@ -333,6 +333,10 @@ cpht_status_t cpht_clear(cpht_table_t t, uint64_t seed, void* stream) {
   DeviceGuard g(t->device);
   if (!g.ok) return CPHT_E_DEVICE;
   derive_perms(t, seed);
+  if (t->d_desc) {  // a table-set view: its set's launches read the device copy
+    hipError_t e = launch_store_desc(t->tk, t->d_desc, as_stream(stream));
+    if (e != hipSuccess) return device_status(e);
+  }
   for (int x = 0; x < t->nimages; ++x) {
     hipError_t e = launch_zero(t->level[x], t->level_words[x], as_stream(stream));
     if (e != hipSuccess) return device_status(e);
@@ -603,7 +607,7 @@ int cpht_variant_info(uint32_t scheme, int i, uint32_t* info) {
 
 cpht_status_t cpht_probe(uint32_t kind, void* d_buf, uint64_t bytes, uint64_t ops, uint64_t seed, uint32_t* d_sink,
                          uint64_t* ops_done, void* stream) {
-  if (kind > 2 || !d_buf || !d_sink || bytes < 4096 || !pow2(bytes) || ops == 0) return CPHT_E_ARG;
+  if (kind > 4 || !d_buf || !d_sink || bytes < 4096 || !pow2(bytes) || ops == 0) return CPHT_E_ARG;
   // whole 256-thread blocks: 16384 operations per block for every kind
   const uint64_t unit = 16384;
   const uint64_t n = (ops + unit - 1) / unit * unit;

@@ -25,6 +25,9 @@ struct cpht_table {
   uint64_t val_bytes[3];
   unsigned long long* d_counter;
   cpht::TableK tk;
+  // Table-set view: the set's device copy of tk, read by its launches (kept
+  // equal to tk by every call that changes tk); null for an owning table.
+  cpht::TableK* d_desc;
   const cpht::IceVariant* ice;
   const cpht::CkVariant* ck;
 };

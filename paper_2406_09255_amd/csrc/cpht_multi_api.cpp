@@ -193,6 +193,7 @@ cpht_status_t cpht_multi_create(uint32_t n_tables, const cpht_config_t* cfgs, ui
       t.level[x] = reinterpret_cast<uint32_t*>(static_cast<char*>(m->arena) + offs[k++]);
       t.tk.lv[x].base = t.level[x];
     }
+    t.d_desc = m->d_descs + i;
     descs[i] = t.tk;
   }
   e = hipMemcpy(m->d_descs, descs.data(), n_tables * sizeof(TableK), hipMemcpyHostToDevice);

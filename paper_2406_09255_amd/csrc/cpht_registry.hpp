@@ -51,7 +51,7 @@ const IceVariant* ice_variants_u32(int* n);
 const IceVariant* ice_variants_u64(int* n);
 
 // Iceberg launchers come from three translation units per key word (compiled
-// in parallel), one entry per CPHT_ICE_LIST position; cpht_registry.cpp
+// in parallel), one entry per CPHT_ICE_LIST position; cpht_registry.hip
 // assembles them into IceVariant records.
 struct IceLaunch4 {
   launch_fn a, b, c, d;

@@ -30,6 +30,7 @@
 
 #include "cpht.h"
 #include "cpht_internal.hpp"
+#include "cpht_tickets.hpp"
 
 using namespace cpht;
 
@@ -79,7 +80,10 @@ struct cpht_server {
 
   std::mutex mu;
   std::condition_variable cv;
-  std::vector<Request> reqs;  // indexed by ticket
+  // request records by ticket; a record is released once its request has
+  // completed and been collected (waited on or polled as done), or once 2^20
+  // later tickets exist
+  TicketTable<Request> reqs{1u << 20};
   std::deque<uint64_t> queue;
   bool stopping = false;
   std::atomic<int> error{0};
@@ -176,6 +180,8 @@ hipError_t launch_direct(cpht_server* s, Slot& slot, const Request& first, uint6
   return hipEventRecord(slot.done, slot.stream);
 }
 
+bool is_done(const Request& r) { return r.t_done != 0; }
+
 bool adjacent(const Request& a, const Request& b, uint64_t key_bytes) {
   return static_cast<const char*>(b.dkeys) == static_cast<const char*>(a.dkeys) + a.n * key_bytes &&
          b.dops == a.dops + a.n && b.dout == a.dout + a.n;
@@ -226,13 +232,15 @@ void dispatcher(cpht_server* s) {
       if (q != hipSuccess) s->error = 1;
       const uint64_t t = now_ns();
       for (uint64_t id : sl.reqs) {
-        s->reqs[id].t_done = t;
-        s->ops_done += s->reqs[id].n;
+        Request* r = s->reqs.find(id);  // pending records are never released
+        r->t_done = t;
+        s->ops_done += r->n;
         ++s->reqs_done;
       }
       if (!s->cfg.zero_copy) ring_release(s, sl.ring_begin + sl.ring_len);
       sl.busy = false;
       sl.reqs.clear();
+      s->reqs.trim(is_done);
       s->cv.notify_all();
     }
     // 2. admit queued requests into free slots while staging has room
@@ -241,10 +249,10 @@ void dispatcher(cpht_server* s) {
       if (s->cfg.zero_copy) {  // a run of back-to-back requests, read and written in place
         std::vector<uint64_t> ids{s->queue.front()};
         s->queue.pop_front();
-        uint64_t total = s->reqs[ids[0]].n;
+        uint64_t total = s->reqs.find(ids[0])->n;
         while (s->cfg.coalesce && !s->queue.empty()) {
-          const Request& last = s->reqs[ids.back()];
-          const Request& next = s->reqs[s->queue.front()];
+          const Request& last = *s->reqs.find(ids.back());
+          const Request& next = *s->reqs.find(s->queue.front());
           if (total + next.n > s->cfg.max_batch_keys || !adjacent(last, next, s->key_bytes)) break;
           ids.push_back(s->queue.front());
           total += next.n;
@@ -253,7 +261,7 @@ void dispatcher(cpht_server* s) {
         sl.busy = true;
         sl.ring_begin = sl.ring_len = 0;
         sl.reqs = ids;
-        const Request first = s->reqs[ids[0]];  // the request table may grow while unlocked
+        const Request first = *s->reqs.find(ids[0]);  // a copy: the table changes while unlocked
         lk.unlock();
         const hipError_t e = launch_direct(s, sl, first, total);
         lk.lock();
@@ -265,7 +273,7 @@ void dispatcher(cpht_server* s) {
       std::vector<uint64_t> ids;
       uint64_t total = 0;
       while (!s->queue.empty()) {
-        const uint64_t n = s->reqs[s->queue.front()].n;
+        const uint64_t n = s->reqs.find(s->queue.front())->n;
         if (!ids.empty() && (!s->cfg.coalesce || total + n > s->cfg.max_batch_keys)) break;
         if (ids.empty() && n > s->cfg.max_batch_keys) {  // a request larger than one launch runs alone
           ids.push_back(s->queue.front());
@@ -289,7 +297,7 @@ void dispatcher(cpht_server* s) {
       sl.reqs = ids;
       std::vector<Request> group;
       group.reserve(ids.size());
-      for (uint64_t id : ids) group.push_back(s->reqs[id]);
+      for (uint64_t id : ids) group.push_back(*s->reqs.find(id));
       lk.unlock();
       const hipError_t e = launch_group(s, sl, begin, group);
       lk.lock();
@@ -302,7 +310,7 @@ void dispatcher(cpht_server* s) {
       // fail everything still queued so waiters return
       const uint64_t t = now_ns();
       while (!s->queue.empty()) {
-        s->reqs[s->queue.front()].t_done = t;
+        s->reqs.find(s->queue.front())->t_done = t;
         s->queue.pop_front();
       }
       s->cv.notify_all();
@@ -427,14 +435,13 @@ cpht_status_t cpht_server_submit(cpht_server_t s, const void* h_keys, const uint
   if (s->error) return CPHT_E_DEVICE;
   if (s->queue.size() >= (1u << 20)) return CPHT_E_BUSY;
   r.t_submit = t_call;
-  *ticket = s->reqs.size();
-  s->reqs.push_back(r);
-  if (n == 0) {
-    s->reqs.back().t_done = r.t_submit;
-  } else {
+  if (n == 0) r.t_done = r.t_submit;  // nothing to do: complete at once
+  *ticket = s->reqs.add(r);
+  if (n) {
     s->queue.push_back(*ticket);
     if (s->queue.size() > s->max_queue) s->max_queue = s->queue.size();
   }
+  s->reqs.trim(is_done);
   s->cv.notify_all();
   return CPHT_OK;
 }
@@ -442,19 +449,31 @@ cpht_status_t cpht_server_submit(cpht_server_t s, const void* h_keys, const uint
 cpht_status_t cpht_server_poll(cpht_server_t s, uint64_t ticket, int* done, uint64_t* latency_ns) {
   if (!s || !done) return CPHT_E_ARG;
   std::lock_guard<std::mutex> lk(s->mu);
-  if (ticket >= s->reqs.size()) return CPHT_E_ARG;
-  const Request& r = s->reqs[ticket];
-  *done = r.t_done != 0;
-  if (latency_ns) *latency_ns = r.t_done ? r.t_done - r.t_submit : 0;
+  const Request* r = s->reqs.find(ticket);
+  if (!r) return CPHT_E_ARG;
+  *done = r->t_done != 0;
+  if (latency_ns) *latency_ns = r->t_done ? r->t_done - r->t_submit : 0;
+  if (*done) {
+    s->reqs.collect(ticket);
+    s->reqs.trim(is_done);
+  }
   return s->error ? CPHT_E_DEVICE : CPHT_OK;
 }
 
 cpht_status_t cpht_server_wait(cpht_server_t s, uint64_t ticket, uint64_t* latency_ns) {
   if (!s) return CPHT_E_ARG;
   std::unique_lock<std::mutex> lk(s->mu);
-  if (ticket >= s->reqs.size()) return CPHT_E_ARG;
-  s->cv.wait(lk, [&] { return s->reqs[ticket].t_done != 0; });
-  if (latency_ns) *latency_ns = s->reqs[ticket].t_done - s->reqs[ticket].t_submit;
+  if (!s->reqs.find(ticket)) return CPHT_E_ARG;
+  // the record can only go away once done and 2^20 later tickets exist
+  s->cv.wait(lk, [&] {
+    const Request* r = s->reqs.find(ticket);
+    return !r || r->t_done != 0;
+  });
+  const Request* r = s->reqs.find(ticket);
+  if (!r) return CPHT_E_ARG;
+  if (latency_ns) *latency_ns = r->t_done - r->t_submit;
+  s->reqs.collect(ticket);
+  s->reqs.trim(is_done);
   return s->error ? CPHT_E_DEVICE : CPHT_OK;
 }
 
@@ -491,6 +510,8 @@ cpht_status_t cpht_server_replay(cpht_server_t s, uint64_t n_requests, const uin
     if (offsets[i + 1] < offsets[i] || (i && arrival_ns[i] < arrival_ns[i - 1])) return CPHT_E_ARG;
   std::vector<uint64_t> tickets(n_requests);
   const uint64_t t0 = now_ns();
+  uint64_t collected = 0;  // requests [0, collected) have their latency
+  cpht_status_t worst = CPHT_OK;
   for (uint64_t i = 0; i < n_requests; ++i) {
     while (now_ns() - t0 < arrival_ns[i]) {  // wait for the request's arrival time
       const uint64_t left = arrival_ns[i] - (now_ns() - t0);
@@ -502,9 +523,17 @@ cpht_status_t cpht_server_replay(cpht_server_t s, uint64_t n_requests, const uin
                                     &tickets[i])) == CPHT_E_BUSY)
       std::this_thread::yield();
     if (st != CPHT_OK) return st;
+    // collect the requests that are done, in order, so that their records
+    // are released however long the trace is
+    while (collected <= i) {
+      int done = 0;
+      const cpht_status_t ps = cpht_server_poll(s, tickets[collected], &done, &latency_ns[collected]);
+      if (ps != CPHT_OK) worst = ps;
+      if (!done) break;
+      ++collected;
+    }
   }
-  cpht_status_t worst = CPHT_OK;
-  for (uint64_t i = 0; i < n_requests; ++i) {
+  for (uint64_t i = collected; i < n_requests; ++i) {
     const cpht_status_t st = cpht_server_wait(s, tickets[i], &latency_ns[i]);
     if (st != CPHT_OK) worst = st;
   }

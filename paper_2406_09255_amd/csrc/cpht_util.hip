@@ -56,6 +56,10 @@ __global__ __launch_bounds__(256) void zero_kernel(uint32_t* base, uint64_t word
 
 __global__ __launch_bounds__(256) void zero_u64_kernel(unsigned long long* p) { *p = 0ull; }
 
+__global__ void desc_kernel(TableK T, TableK* dst) {
+  if (threadIdx.x == 0) *dst = T;
+}
+
 // a_i(k) and the stored form r'_i(k) with tag `tag` at level `level`.
 template <class U, int S>
 __global__ __launch_bounds__(256) void split_kernel(TableK T, int level, int i, uint32_t tag, const U* keys,
@@ -89,6 +93,11 @@ hipError_t launch_zero(uint32_t* base, uint64_t words, hipStream_t s) {
 
 hipError_t launch_zero_counter(unsigned long long* p, hipStream_t s) {
   hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_store_desc(const TableK& T, TableK* dst, hipStream_t s) {
+  hipLaunchKernelGGL(desc_kernel, dim3(1), dim3(64), 0, s, T, dst);
   return hipGetLastError();
 }
 

@@ -96,6 +96,54 @@ def test_table_set_equals_separate_tables(gpu):
     assert np.array_equal(f_set, f_one)
 
 
+@pytest.mark.parametrize("scheme", [cpht.ICEBERG, cpht.CUCKOO])
+def test_reseeded_view_is_used_by_set_launches(gpu, scheme):
+    """cpht_clear with a new seed on one table's view: keys inserted through
+    the view (single-table call, new permutations) are found by the set-wide
+    find, and keys inserted by the set-wide insert afterwards are found
+    through the view; answers as the oracle's table with the new seed."""
+    w = 32
+    cfgs = _configs(12, 17, scheme)
+    keys, ko, q, qo, per = _batches(cfgs, w, 0.6, 2, 55)
+    m = cpht.MultiTable(cfgs, max_keys=max(keys.numel(), q.numel()))
+    dk, dko = synth.to_words(keys, w).to(gpu), ko.to(gpu)
+    dq, dqo = synth.to_words(q, w).to(gpu), qo.to(gpu)
+    m.insert(dk, dko)
+    i = 5
+    v = m.table(i)
+    v.clear(0xABCDEF)
+    a, b = int(ko[i]), int(ko[i + 1])
+    half = a + (b - a) // 2
+    assert (v.insert(dk[a:half]) == cpht.PUT).all()
+    found = m.find(dq, dqo).cpu().numpy()
+    c = v.config
+    assert c.seed == 0xABCDEF
+    o = oracle.Table(c.scheme, c.key_bits, c.log2_slots0, c.bucket0, c.slot_bits0, log2_slots1=c.log2_slots1,
+                     B1=c.bucket1, s1=c.slot_bits1, H=c.n_hash, C=c.max_chain, compact=bool(c.compact), seed=c.seed)
+    hk = host_u64(keys)
+    assert (o.insert(hk[a:half]) == oracle.PUT).all()
+    hq = host_u64(q)
+    qa, qb = int(qo[i]), int(qo[i + 1])
+    assert np.array_equal(found[qa:qb], o.find(hq[qa:qb]))
+    assert np.array_equal(check_table(v), np.sort(hk[a:half]))
+    # the other tables kept their seeds and contents
+    for j in (0, 11):
+        ja, jb = int(qo[j]), int(qo[j + 1])
+        S = np.sort(host_u64(per[j]))
+        assert np.array_equal(found[ja:jb], sets.find(S, hq[ja:jb]))
+    # the set-wide insert places keys by the new permutations as well
+    sub_off = torch.zeros(len(cfgs) + 1, dtype=torch.int64)
+    sub_off[i + 1:] = b - half
+    sub = dk[half:b].contiguous()
+    out = m.insert(sub, sub_off.to(gpu)).cpu().numpy()
+    assert (out == cpht.PUT).all()
+    assert (o.insert(hk[half:b]) == oracle.PUT).all()
+    assert (v.find(dk[a:b]) == 1).all()
+    ok, msg, dec = o.check()
+    assert ok, msg
+    assert np.array_equal(check_table(v), dec)
+
+
 def test_table_set_in_captured_graph(gpu):
     """insert + find of every table captured once and replayed; each replay
     (with an eager clear between replays) must equal the eager run."""

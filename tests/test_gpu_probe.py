@@ -33,6 +33,25 @@ def test_probe_cas_writes_only_claimed_words(gpu):
     assert int((buf != 0).sum()) >= nz.numel()
 
 
+def test_probe_cas64_and_split(gpu):
+    """64-bit CAS claims 8-byte words with odd tags and nothing else; the
+    split probe reads its keys and leaves them alone."""
+    buf = torch.zeros(1 << 19, dtype=torch.int64, device=gpu)  # 4 MiB
+    sink = torch.zeros(1, dtype=torch.int32, device=gpu)
+    done = cpht.probe(cpht.PROBE_CAS64, buf, 1 << 16, 11, sink)
+    torch.cuda.synchronize()
+    assert done == 1 << 16
+    nz = buf[buf != 0]
+    assert 0 < nz.numel() <= done
+    assert bool(((nz & 1) == 1).all())
+    keys = synth.distinct_keys(37, 5, 0, 1 << 18, device=gpu).contiguous()
+    before = keys.clone()
+    done = cpht.probe(cpht.PROBE_SPLIT, keys, 1 << 20, 3, sink)
+    torch.cuda.synchronize()
+    assert done == 1 << 20
+    assert torch.equal(keys, before)
+
+
 def test_probe_rejects_bad_buffers(gpu):
     sink = torch.zeros(1, dtype=torch.int32, device=gpu)
     with pytest.raises(cpht.CphtError):  # not a power of two
