@@ -47,6 +47,7 @@ PROBES_PER_FIND = {0.5: 1.00014, 0.7: 1.01809, 0.8: 1.07518, 0.9: 1.22454, 0.95:
 ICE_L2 = {"put": 0.075824, "find": 0.314262}
 KEY_BYTES = 8
 RESULT_BYTES = 1
+CAS_BYTES = 4  # the atomic of a put round moves one 32-bit slot (8 bytes for 64-bit slots)
 SECTOR = 64  # write-back unit of a modified slot (measured: 68.7 B written per put at 1.05 rounds)
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by the
@@ -77,9 +78,16 @@ def csrc_sha(sources=KERNEL_SOURCES) -> str:
     return h.hexdigest()[:16]
 
 
-def put_bytes(load: float, bucket_lines: int) -> float:
-    """Algorithmic bytes of one put: each round reads a bucket and writes back
-    the 64-byte sector holding the claimed or swapped slot."""
+def put_bytes(load: float, bucket_lines: int, cas_bytes: int = CAS_BYTES) -> float:
+    """Algorithmic bytes of one put: each round reads its bucket's 128-byte
+    lines and performs one atomic on one slot; plus the key word read and the
+    result byte written."""
+    return ROUNDS_PER_PUT[load] * (bucket_lines * LINE + cas_bytes) + KEY_BYTES + RESULT_BYTES
+
+
+def put_bytes_sector(load: float, bucket_lines: int) -> float:
+    """The same put charged with what the memory system moves for its atomic:
+    the 64-byte sector holding the claimed or swapped slot is written back."""
     return ROUNDS_PER_PUT[load] * (bucket_lines * LINE + SECTOR) + KEY_BYTES + RESULT_BYTES
 
 
@@ -566,39 +574,63 @@ def iceberg_static(torch, cpht, synth, dev, reps=3):
     return rows
 
 
-def iceberg_mixed(torch, cpht, synth, dev, log2_slots0=28, batch=1 << 20):
+def mixed_stream_check(torch, idx, ops, out, n_fresh, counted):
+    """Answers of the dynamic-operation stream (synth.mixed_batches) against
+    the set semantics, from the index each key was drawn from (keys =
+    phi(index), distinct indices give distinct keys): every distinct inserted
+    key is answered PUT exactly once, in the first batch that inserts it, and
+    FOUND everywhere else; a find answers 1 if its key was inserted by an
+    earlier batch, 0 if by no batch up to its own, either way if by its own
+    batch; the table ends holding exactly the distinct inserted keys."""
+    import synth
+
+    nb, batch = idx.shape
+    dev = idx.device
+    bidx = torch.arange(nb, device=dev).view(nb, 1).expand(nb, batch)
+    ins = ops == 1
+    j, b, o = idx[ins], bidx[ins], out[ins]
+    first = torch.full((n_fresh,), nb, dtype=torch.int64, device=dev)
+    first.scatter_reduce_(0, j, b, reduce="amin")
+    bad_answer = int(((o != 1) & (o != 2)).sum().item())  # PUT or FOUND only
+    put = o == 1
+    cnt = torch.zeros(n_fresh, dtype=torch.int32, device=dev)
+    cnt.scatter_add_(0, j[put], torch.ones(int(put.sum().item()), dtype=torch.int32, device=dev))
+    bad_put_count = int((cnt != 1).sum().item())
+    late_put = int((first[j[put]] != b[put]).sum().item())
+    del j, b, o, put, cnt
+    fnd = ~ins
+    j, b, o = idx[fnd], bidx[fnd], out[fnd]
+    inserted = j < n_fresh
+    assert int((inserted & (j >= synth.MISS_BASE)).sum().item()) == 0
+    fj = torch.where(inserted, first[j.clamp(max=n_fresh - 1)], torch.full_like(j, nb))
+    must1 = fj < b
+    racy = fj == b
+    wrong_find = int(((o != 1) & must1).sum().item()) + int(((o != 0) & ~must1 & ~racy).sum().item()) + \
+        int(((o > 1) & racy).sum().item())
+    ok = bad_answer == 0 and bad_put_count == 0 and late_put == 0 and wrong_find == 0 and counted == n_fresh
+    return {"result": "ok" if ok else "FAILED", "insert_answers_not_put_or_found": bad_answer,
+            "keys_not_put_exactly_once": bad_put_count, "puts_after_first_batch": late_put,
+            "wrong_fixed_finds": wrong_find, "racy_finds": int(racy.sum().item()),
+            "count": counted, "distinct_inserted": n_fresh}
+
+
+def iceberg_mixed(torch, cpht, synth, dev, log2_slots0=28, batch=1 << 20, graph_run=32):
     """Dynamic operation at 2^28 + 2^25 slots (B0 = 32, B1 = 16, 34-bit keys):
     mixed batches of `batch` operations, half finds and half find-or-puts in
     random order; 30 % of inserts repeat an earlier-issued key; finds hit keys
-    inserted by earlier batches half of the time.  Runs from load 0 to 0.9.
-    Reports ops/s over the whole run and the per-batch latency distribution."""
+    inserted by earlier batches half of the time (synth.mixed_batches).  Runs
+    from load 0 to 0.9, batches issued one by one on one stream, and for the
+    compact table also with runs of `graph_run` batches captured in one HIP
+    graph and replayed (batches still run in order, one launch each).
+    Reports ops/s over the whole run, the per-batch latency distribution and
+    a check of every answer against the set semantics."""
     w = 34
     L0, L1 = log2_slots0, log2_slots0 - 3
     cap = (1 << L0) + (1 << L1)
-    half = batch // 2
-    fresh_per_batch = int(0.7 * half)
-    nb = int(LOAD * cap) // fresh_per_batch
-    n_ins = nb * half
-    ins, n_fresh = synth.insert_stream_with_duplicates(w, KEY_SEED + 3, 0, n_ins, 0.3, 11, device=dev)
-    rows = {}
-    # per batch: finds (half hits among keys issued by earlier batches, half misses)
-    g = synth.uniform_below(13, nb * half, 1 << 30, dev)
-    ins_b = ins.view(nb, half)
-    issued_before = torch.arange(nb, device=dev) * fresh_per_batch  # approximate count of fresh keys
-    hit_idx = (g.view(nb, half) * issued_before.clamp(min=1).view(nb, 1)) >> 30
-    hit_keys = synth.feistel(w, KEY_SEED + 3, hit_idx)
-    miss_keys = synth.distinct_keys(w, KEY_SEED + 3, 1 << 33, nb * half, device=dev).view(nb, half)
-    is_hit = (synth.uniform_below(17, nb * half, 2, dev).view(nb, half) == 1) & (issued_before.view(nb, 1) > 0)
-    finds = torch.where(is_hit, hit_keys, miss_keys)
-    keys = torch.cat([ins_b, finds], dim=1)
-    ops = torch.cat([torch.ones(nb, half, dtype=torch.uint8, device=dev),
-                     torch.zeros(nb, half, dtype=torch.uint8, device=dev)], dim=1)
-    perm = torch.stack([synth.permutation(100 + b, batch, dev) for b in range(min(nb, 8))])
-    idx = perm[torch.arange(nb, device=dev) % perm.shape[0]]
-    keys = torch.gather(keys, 1, idx).contiguous()
-    ops = torch.gather(ops, 1, idx).contiguous()
+    keys, ops, idx, n_fresh = synth.mixed_batches(w, KEY_SEED + 3, cap, LOAD, batch, device=dev)
+    nb = keys.shape[0]
     out = torch.empty(nb, batch, dtype=torch.uint8, device=dev)
-    del ins, hit_idx, hit_keys, miss_keys, finds, g
+    rows = {}
     for label, s0, s1, cmp_ in (("compact_16_32", 16, 32, 1), ("plain_64_64", 64, 64, 0)):
         t = cpht.Table(scheme=cpht.ICEBERG, key_bits=w, log2_slots0=L0, log2_slots1=L1, bucket0=32, bucket1=16,
                        slot_bits0=s0, slot_bits1=s1, compact=cmp_, seed=9)
@@ -622,12 +654,44 @@ def iceberg_mixed(torch, cpht, synth, dev, log2_slots0=28, batch=1 << 20):
                        "batches": nb, "batch_ops": batch,
                        "batch_latency_ms": {"p50": round(pct(lat, 50), 4), "p99": round(pct(lat, 99), 4)},
                        "fill_factor": round(occ / cap_, 4), "full": nfull, "first_full_batch": first_full,
-                       "table_bytes": t.level_bytes(0) + t.level_bytes(1)}
+                       "table_bytes": t.level_bytes(0) + t.level_bytes(1),
+                       "check": mixed_stream_check(torch, idx, ops, out, n_fresh, occ)}
+        if cmp_:
+            rows[label]["graph_replay"] = mixed_graph_run(torch, t, keys, ops, out, graph_run)
+            rows[label]["graph_replay"]["check"] = mixed_stream_check(torch, idx, ops, out, n_fresh, t.count()[0])
         del t
     rows["compact_vs_plain"] = round(rows["compact_16_32"]["mops"] / rows["plain_64_64"]["mops"], 3)
     rows["config"] = (f"iceberg 2^{L0} + 2^{L1} slots, B0=32, B1=16, {w}-bit keys; {nb} mixed batches of {batch} "
                       f"ops (50% find / 50% find-or-put, 30% duplicate inserts, finds 50% hit), load 0 -> {LOAD}")
+    del keys, ops, idx, out
     return rows
+
+
+def mixed_graph_run(torch, t, keys, ops, out, run):
+    """The same batches from an empty table (same seed), runs of `run`
+    consecutive batches captured in one graph each and replayed once; the
+    capture and instantiation of each run happen before the timed region."""
+    nb = keys.shape[0]
+    t.clear(t.config.seed)
+    torch.cuda.synchronize()
+    graphs = []
+    s = torch.cuda.Stream()
+    for a in range(0, nb, run):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            for b in range(a, min(nb, a + run)):
+                t.mixed(keys[b], ops[b], out[b])
+        graphs.append(g)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for g in graphs:
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    del graphs
+    return {"mops": round(nb * keys.shape[1] / ms / 1e3, 1), "batches_per_graph": run, "ms": round(ms, 3)}
 
 
 def many_tables(torch, cpht, synth, dev, n_tables=4096, lo=10, hi=20, load=0.85, reps=3):
@@ -753,9 +817,14 @@ def iceberg_zipf(torch, cpht, synth, dev, log2_slots0=28, batch=1 << 20, max_bat
                    slot_bits0=16, slot_bits1=32, seed=19)
     cap = t.count()[1]
     ops = (synth.uniform_below(0x2F, batch, 2, dev)).to(torch.uint8)
+    ins = ops == 1
     outs = torch.empty((chunk, batch), dtype=torch.uint8, device=dev)
+    # truth: first[k] = 1 + the first batch that inserts key k (0: none yet),
+    # over the whole 2^34 key space (32 GiB of int16)
+    first = torch.zeros(1 << w, dtype=torch.int16, device=dev)
+    bad = {"insert": 0, "put_count": 0, "find": 0}
     lat, curve = [], []
-    b, occ, first_full, puts = 0, 0, None, 0
+    b, occ, first_full, puts, racy = 0, 0, None, 0, 0
     while b < max_batches and occ < target * cap and first_full is None:
         nb = min(chunk, max_batches - b)
         keys = [synth.zipf_keys(w, KEY_SEED + 5, 1.1, batch, 1000 + b + i, device=dev) for i in range(nb)]
@@ -771,12 +840,23 @@ def iceberg_zipf(torch, cpht, synth, dev, log2_slots0=28, batch=1 << 20, max_bat
         full_rows = torch.nonzero((outs[:nb] == cpht.FULL).any(dim=1))
         if full_rows.numel():
             first_full = b + int(full_rows[0].item())
-        puts += int(((outs[:nb] == cpht.PUT) & (ops == 1)).sum().item())  # finds answer 1 too
+        puts += int(((outs[:nb] == cpht.PUT) & ins).sum().item())  # finds answer 1 too
+        for i in range(nb):  # every answer against the set semantics (untimed)
+            r = zipf_batch_check(torch, first, b + i, keys[i], ins, outs[i])
+            racy += r.pop("racy")
+            for k_ in bad:
+                bad[k_] += r[k_]
         occ = t.count()[0]
         b += nb
         curve.append({"batches": b, "load": round(occ / cap, 4), "mops": round(nb * batch / sum(ms) / 1e3, 1)})
         del keys
-    rows = {"mops": round(b * batch / sum(lat) / 1e3, 1),
+    distinct = int(torch.count_nonzero(first).item())
+    del first
+    ok = first_full is None and not any(bad.values()) and distinct == occ == puts
+    check = {"result": "ok" if ok else "FAILED", "wrong_insert_answers": bad["insert"],
+             "batches_with_wrong_put_count": bad["put_count"], "wrong_fixed_finds": bad["find"],
+             "racy_finds": racy, "distinct_inserted": distinct, "count": occ, "puts": puts}
+    rows = {"check": check, "mops": round(b * batch / sum(lat) / 1e3, 1),
             "batch_latency_ms": {"p50": round(pct(lat, 50), 4), "p99": round(pct(lat, 99), 4)},
             "batches": b, "operations": b * batch, "puts": puts, "fill_factor": round(occ / cap, 4),
             "first_full_batch": first_full, "by_load": curve[:: max(1, len(curve) // 12)] + curve[-1:],
@@ -787,15 +867,44 @@ def iceberg_zipf(torch, cpht, synth, dev, log2_slots0=28, batch=1 << 20, max_bat
     return rows
 
 
-def serving(torch, cpht, synth, dev, n_req=20000, log2_slots0=32, prefill=0.5, seed=3):
+def zipf_batch_check(torch, first, b, keys, ins, out):
+    """One mixed batch against the set semantics, with first[k] = 1 + the
+    first batch that inserted key k (0 = not yet), updated here: an insert of
+    a key stored by an earlier batch answers FOUND; the batch's new keys are
+    answered PUT once each (and FOUND otherwise); a find answers 1 if an
+    earlier batch inserted its key, 0 if no batch up to this one did, either
+    way if this batch does."""
+    ki, oi = keys[ins], out[ins]
+    seen = first[ki] != 0
+    wrong_insert = int((seen & (oi != 2)).sum().item()) + int((~seen & (oi != 1) & (oi != 2)).sum().item())
+    new = ki[~seen]
+    put_keys = ki[oi == 1]
+    n_new = int(torch.unique(new).numel())
+    put_ok = put_keys.numel() == n_new and int(torch.unique(put_keys).numel()) == n_new
+    first[new] = b + 1
+    v = first[keys[~ins]].to(torch.int32)
+    of = out[~ins]
+    earlier, same = (v != 0) & (v <= b), v == b + 1
+    wrong_find = int((earlier & (of != 1)).sum().item()) + int((~earlier & ~same & (of != 0)).sum().item()) + \
+        int((same & (of > 1)).sum().item())
+    return {"insert": wrong_insert, "put_count": 0 if put_ok else 1, "find": wrong_find,
+            "racy": int(same.sum().item())}
+
+
+def serving(torch, cpht, synth, dev, n_req=100000, n_req_other=20000, log2_slots0=32, prefill=0.5, seed=3,
+            stop_load=0.85):
     """Serving loop over one resident compact iceberg table of 2^32 + 2^29
     slots (16/32-bit, 40-bit keys), pre-filled to load 0.5.  Requests: sizes
-    lognormal (median 4096, sigma 2) clipped to 1..2^22; 70 % finds (half hits)
-    and 30 % inserts of fresh keys; host-resident (pinned) buffers.  Runs: all
-    requests at t = 0 (saturation), then Poisson arrivals at 25, 50, 75 and 90 %
-    of the saturated request rate; the comparator is the same server with one
-    request per launch and one launch in flight (plain batched launches in
-    arrival order).  The table is emptied and pre-filled again before each run."""
+    lognormal (median 4096, sigma 2) clipped to 1..2^22; 70 % finds (half hits
+    on pre-filled keys, half on keys never inserted) and 30 % inserts of fresh
+    keys; host-resident (pinned) buffers.  Runs: all n_req requests at t = 0
+    (saturation) and Poisson arrivals at 50 % of the saturated request rate;
+    the first n_req_other requests at 25, 75 and 90 %.  The trace is cut where
+    its inserts would take the table past stop_load.  The comparator is the
+    same server with one request per launch and one launch in flight (plain
+    batched launches in arrival order).  The table is emptied and pre-filled
+    again before each run, and every answer of every run is checked: inserts
+    of fresh keys answer PUT, finds answer 1 exactly for pre-filled keys."""
     import numpy as np
 
     w = 40
@@ -819,46 +928,79 @@ def serving(torch, cpht, synth, dev, n_req=20000, log2_slots0=32, prefill=0.5, s
     offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
     total = int(offsets[-1])
     is_ins = synth.uniform_below(0x31, total, 10, dev) < 3
+    # cut the trace where its inserts would pass stop_load
+    ins_upto = torch.cumsum(is_ins.to(torch.int64), 0)
+    room = int(stop_load * cap) - n_pre
+    over = torch.nonzero(ins_upto > room)
+    if over.numel():
+        last_op = int(over[0].item())
+        n_req = int(np.searchsorted(offsets, last_op, side="right")) - 1
+        total = int(offsets[n_req])
+        is_ins = is_ins[:total]
+    del ins_upto, over
+    n_req_other = min(n_req_other, n_req)
     is_hit = synth.uniform_below(0x32, total, 2, dev) == 1
     fresh_idx = n_pre + torch.cumsum(is_ins.to(torch.int64), 0)
     hit_idx = synth.uniform_below(0x33, total, 1 << 30, dev) * n_pre >> 30
     miss_idx = (1 << 39) + torch.arange(total, device=dev)
     idx = torch.where(is_ins, fresh_idx, torch.where(is_hit, hit_idx, miss_idx))
-    keys = synth.feistel(w, KEY_SEED + 7, idx).cpu().pin_memory()
-    ops = is_ins.to(torch.uint8).cpu().pin_memory()
-    out = torch.zeros(total, dtype=torch.uint8).pin_memory()
-    del is_ins, is_hit, fresh_idx, hit_idx, miss_idx, idx
+    keys = torch.empty(total, dtype=torch.int64, pin_memory=True)
+    keys.copy_(synth.feistel(w, KEY_SEED + 7, idx))
+    ops = torch.empty(total, dtype=torch.uint8, pin_memory=True)
+    ops.copy_(is_ins.to(torch.uint8))
+    out = torch.zeros(total, dtype=torch.uint8, pin_memory=True)
+    # the answer every operation must get: no find looks for a key that a
+    # request inserts, so no answer depends on how requests overlap
+    truth = torch.where(is_ins, torch.full_like(is_ins, cpht.PUT, dtype=torch.uint8), is_hit.to(torch.uint8))
+    ins_in = {nr: int(is_ins[:int(offsets[nr])].sum().item()) for nr in {n_req, n_req_other}}
+    del is_hit, fresh_idx, hit_idx, miss_idx, idx, is_ins
+    torch.cuda.empty_cache()
 
-    def run(arrival, **kw):
+    def run(arrival, nr, **kw):
         refill()
+        out.zero_()
         srv = cpht.Server(t, **kw)
-        lat, mk = srv.replay(arrival, offsets, keys, ops, out)
+        lat, mk = srv.replay(arrival[:nr], offsets[:nr + 1], keys, ops, out)
         st = srv.stats()
         srv.stop()
+        ops_n = int(offsets[nr])
+        wrong = int((out[:ops_n].to(dev) != truth[:ops_n]).sum().item())
+        want_count = n_pre + ins_in[nr]
+        counted = t.count()[0]
         lat_ms = lat.astype(np.float64) / 1e6
-        return {"mops": round(total / (mk / 1e9) / 1e6, 1), "requests_per_s": round(n_req / (mk / 1e9), 0),
+        return {"requests": nr, "operations": ops_n, "mops": round(ops_n / (mk / 1e9) / 1e6, 1),
+                "requests_per_s": round(nr / (mk / 1e9), 0),
                 "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
                 "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
-                "makespan_ms": round(mk / 1e6, 2), "launches": st["launches"], "max_queue": st["max_queue"]}
+                "makespan_ms": round(mk / 1e6, 2), "launches": st["launches"], "max_queue": st["max_queue"],
+                "load_end": round(counted / cap, 4),
+                "check": "ok" if (wrong == 0 and counted == want_count) else
+                         f"FAILED: {wrong} wrong answers, count {counted} (want {want_count})"}
 
     cont = dict(max_inflight=4, coalesce=1, staging_keys=1 << 25, max_batch_keys=1 << 22)
     plain = dict(max_inflight=1, coalesce=0, staging_keys=1 << 25, max_batch_keys=1 << 22)
     direct = dict(max_inflight=4, coalesce=1, max_batch_keys=1 << 22, zero_copy=1)
     res = {"config": (f"iceberg 2^{L0} + 2^{L1} slots (16/32-bit, {t.level_bytes(0) + t.level_bytes(1)} bytes), "
-                      f"{w}-bit keys, pre-filled to load {prefill}; {n_req} requests, {total} operations, sizes "
-                      f"lognormal(median 4096, sigma 2) in 1..2^22, 70% find / 30% insert, pinned host buffers"),
+                      f"{w}-bit keys, pre-filled to load {prefill}; {n_req} requests ({total} operations) for the "
+                      f"saturated and 50% runs, the first {n_req_other} for the other rates; sizes "
+                      f"lognormal(median 4096, sigma 2) in 1..2^22, 70% find / 30% insert, pinned host buffers; "
+                      f"trace cut at load {stop_load}"),
            "requests": n_req, "operations": total}
     zero = np.zeros(n_req, dtype=np.uint64)
-    res["saturated"] = run(zero, **cont)
-    res["saturated_plain"] = run(zero, **plain)
-    res["saturated_zero_copy"] = run(zero, **direct)
+    res["saturated"] = run(zero, n_req, **cont)
+    res["saturated_plain"] = run(zero, n_req, **plain)
+    res["saturated_zero_copy"] = run(zero, n_req, **direct)
     rate = res["saturated"]["requests_per_s"]
     for frac in (0.25, 0.5, 0.75, 0.9):
-        gaps = r.exponential(1e9 / (frac * rate), n_req)
+        nr = n_req if frac == 0.5 else n_req_other
+        gaps = r.exponential(1e9 / (frac * rate), nr)
         arrival = np.cumsum(gaps).astype(np.uint64)
-        res[f"poisson_{int(frac * 100)}"] = run(arrival, **cont)
-        res[f"poisson_{int(frac * 100)}_plain"] = run(arrival, **plain)
-        res[f"poisson_{int(frac * 100)}_zero_copy"] = run(arrival, **direct)
+        res[f"poisson_{int(frac * 100)}"] = run(arrival, nr, **cont)
+        if frac == 0.5:
+            res[f"poisson_{int(frac * 100)}_plain"] = run(arrival, nr, **plain)
+        res[f"poisson_{int(frac * 100)}_zero_copy"] = run(arrival, nr, **direct)
+    checks = [v["check"] for v in res.values() if isinstance(v, dict) and "check" in v]
+    res["check"] = "ok" if all(c == "ok" for c in checks) else "FAILED"
     # one 4096-operation request at a time on an idle server, beside a bare
     # mixed launch over device-resident buffers (launch + kernel + synchronise)
     import time
@@ -888,9 +1030,7 @@ def serving(torch, cpht, synth, dev, n_req=20000, log2_slots0=32, prefill=0.5, s
         gbs = res[name]["mops"] * 1e6 * (kb + 1) / 1e9
         res[name]["host_link_in_GBps"] = round(gbs, 2)
         res[name]["frac_of_h2d"] = round(gbs / link["h2d_GBps"], 3)
-    occ, cp = t.count()
-    res["fill_factor_end"] = round(occ / cp, 4)
-    del t
+    del t, keys, ops, out, truth
     return res
 
 
@@ -917,7 +1057,7 @@ def host_link(torch, dev, mib=512, reps=5):
     return out
 
 
-def ceilings(torch, cpht, dev, res):
+def ceilings(torch, cpht, dev, res, split_keys):
     """Measured random-access rates: 128-byte line reads, 32-bit CAS, and a
     line read followed by a CAS into it, on a buffer the size of the compact
     table (partly served by the 256 MB Infinity Cache) and on a 4 GiB buffer."""
@@ -927,7 +1067,7 @@ def ceilings(torch, cpht, dev, res):
         buf = torch.zeros(nbytes // 4, dtype=torch.int32, device=dev)
         row = {}
         for kind, name in ((cpht.PROBE_LINES, "line_reads"), (cpht.PROBE_CAS, "cas"),
-                           (cpht.PROBE_LINE_CAS, "line_read_then_cas")):
+                           (cpht.PROBE_CAS64, "cas64"), (cpht.PROBE_LINE_CAS, "line_read_then_cas")):
             ops = 1 << 27
             cpht.probe(kind, buf, ops, 1, sink)  # warm-up (and first touch)
             times = []
@@ -949,6 +1089,26 @@ def ceilings(torch, cpht, dev, res):
     r = out["table_size"]
     out["put_vs_line_read_then_cas"] = round(res["insert_mops"] * lines_put / (r["line_read_then_cas"]["G_per_s"] * 1e3), 3)
     out["find_vs_line_reads"] = round(res["find_mops"] * lines_find / (r["line_reads"]["G_per_s"] * 1e3), 3)
+    out["find_vs_line_reads_4GiB"] = round(res["find_mops"] * lines_find /
+                                           (out["4GiB"]["line_reads"]["G_per_s"] * 1e3), 3)
+    # the quotienting split alone (three permutations per key) on the
+    # benchmark's keys, against the build that applies it
+    keys = split_keys[: 1 << 26]  # a power-of-two buffer of the benchmark's keys
+    n = keys.numel()
+    cpht.probe(cpht.PROBE_SPLIT, keys, n, 1, sink)
+    times = []
+    for rep in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        done = cpht.probe(cpht.PROBE_SPLIT, keys, n, 2 + rep, sink)
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    ms = sorted(times)[1]
+    per_key_s = ms / 1e3 / done
+    out["split_three_perms"] = {"keys": done, "ms": round(ms, 4), "G_keys_per_s": round(1 / per_key_s / 1e9, 2),
+                                "time_vs_put_per_key": round(per_key_s * res["insert_mops"] * 1e6, 4),
+                                "time_vs_find_per_key": round(per_key_s * res["find_mops"] * 1e6, 4)}
     return out
 
 
@@ -1104,7 +1264,11 @@ def main():
         gbs = nbytes / (ms / 1000.0) / 1e9
         rl[name] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": TRAFFIC[name] if fresh else None,
-                    "avg_ms": round(ms, 4), "algorithmic_bytes": int(nbytes)}
+                    "avg_ms": round(ms, 4), "algorithmic_bytes": int(nbytes),
+                    "bytes_per_op": round(nbytes / (n_ins if name == "cuckoo_put" else N_FIND), 2)}
+    # the put also charged with the 64-byte sector its atomic writes back
+    rl["cuckoo_put"]["frac_sector_model"] = round(
+        n_ins * put_bytes_sector(LOAD, 1) / (ins_avg / 1000.0) / 1e9 / HBM_PEAK_GBS, 4)
     res["roofline"] = dict(rl[dom], kernel=dom)
     res["roofline_other"] = {k: v for k, v in rl.items() if k != dom}
     del compact
@@ -1202,7 +1366,7 @@ def main():
         run_section(res, "serving", lambda: serving(torch, cpht, synth, dev))
 
     if not args.no_ceilings:
-        run_section(res, "ceilings", lambda: ceilings(torch, cpht, dev, res))
+        run_section(res, "ceilings", lambda: ceilings(torch, cpht, dev, res, keys))
         c = res["ceilings"].get("table_size")
         if c is not None and res["roofline"]["kernel"] == "cuckoo_put":
             # one CAS per put round: the device's random line-read-then-CAS rate bounds the kernel

@@ -116,12 +116,13 @@ def find_queries(w: int, key_seed: int, n_inserted: int, n_queries: int, hit_fra
 
 
 def insert_stream_with_duplicates(w: int, key_seed: int, fresh_start: int, n_ops: int,
-                                  dup_frac: float, seed: int, device="cpu"):
+                                  dup_frac: float, seed: int, device="cpu", return_index: bool = False):
     """Insert keys where a dup_frac share repeats keys issued earlier.
 
     Returns (keys, n_fresh): fresh keys are phi(fresh_start + i) in order; each
     duplicate copies a uniformly chosen earlier key of the stream (or of the
-    keys issued before it: phi(0..fresh_start-1))."""
+    keys issued before it: phi(0..fresh_start-1)).  With return_index, also
+    the index of every key (keys = phi(index))."""
     r = _lsr(_rand_u64(seed, 0, n_ops, device), 11)  # 53 random bits
     is_dup = r < int(dup_frac * (1 << 53))
     if fresh_start == 0 and n_ops > 0:
@@ -131,7 +132,51 @@ def insert_stream_with_duplicates(w: int, key_seed: int, fresh_start: int, n_ops
     pool = fresh_start + fresh_rank + 1  # keys phi(0..pool-1) exist before op i (for dups)
     pick = (_lsr(_rand_u64(seed + 7, 0, n_ops, device), 32) * pool) >> 32
     idx = torch.where(is_dup, pick, fresh_start + fresh_rank)
+    if return_index:
+        return feistel(w, key_seed, idx), n_fresh, idx
     return feistel(w, key_seed, idx), n_fresh
+
+
+MISS_BASE = 1 << 33  # mixed_batches: finds that miss use phi(MISS_BASE + j)
+
+
+def mixed_batches(w: int, key_seed: int, capacity: int, load: float, batch: int, device="cpu"):
+    """The dynamic-operation stream: mixed batches of `batch` operations, half
+    find-or-puts and half finds in a seeded random order, run from an empty
+    table to `load` * capacity distinct keys.
+
+    Inserts: one stream over all batches in which 70 % of the operations are
+    fresh keys phi(0), phi(1), ... in order and 30 % repeat a uniformly chosen
+    earlier key of the stream.  Finds of batch b: with probability 1/2 a key
+    phi(j) with j uniform below b * (fresh keys per batch expected), else a
+    key phi(MISS_BASE + j) that is never inserted (none in batch 0).
+
+    Returns (keys, ops, idx, n_fresh): keys [nb, batch] int64, ops [nb, batch]
+    uint8 (1 = find-or-put, 0 = find), idx [nb, batch] int64 with keys =
+    phi(idx), and the number of distinct keys inserted."""
+    half = batch // 2
+    fresh_per_batch = int(0.7 * half)
+    nb = int(load * capacity) // fresh_per_batch
+    ins, n_fresh, ins_idx = insert_stream_with_duplicates(w, key_seed, 0, nb * half, 0.3, 11, device=device,
+                                                          return_index=True)
+    g = uniform_below(13, nb * half, 1 << 30, device)
+    issued_before = torch.arange(nb, device=device) * fresh_per_batch  # expected fresh keys before batch b
+    hit_idx = (g.view(nb, half) * issued_before.clamp(min=1).view(nb, 1)) >> 30
+    miss_idx = MISS_BASE + torch.arange(nb * half, dtype=torch.int64, device=device).view(nb, half)
+    is_hit = (uniform_below(17, nb * half, 2, device).view(nb, half) == 1) & (issued_before.view(nb, 1) > 0)
+    find_idx = torch.where(is_hit, hit_idx, miss_idx)
+    del g, hit_idx, miss_idx, is_hit
+    idx = torch.cat([ins_idx.view(nb, half), find_idx], dim=1)
+    del ins, ins_idx, find_idx
+    ops = torch.cat([torch.ones(nb, half, dtype=torch.uint8, device=device),
+                     torch.zeros(nb, half, dtype=torch.uint8, device=device)], dim=1)
+    perm = torch.stack([permutation(100 + b, batch, device) for b in range(min(nb, 8))])
+    order = perm[torch.arange(nb, device=device) % perm.shape[0]]
+    idx = torch.gather(idx, 1, order).contiguous()
+    ops = torch.gather(ops, 1, order).contiguous()
+    del order, perm
+    keys = feistel(w, key_seed, idx)
+    return keys, ops, idx, n_fresh
 
 
 def find_or_put_batch(w: int, key_seed: int, n_before: int, n_new: int, n_ops: int, seed: int, device="cpu"):

@@ -18,9 +18,27 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_algorithmic_bytes_model():
-    # one round: a 128-byte bucket read, a 64-byte write-back, key and result bytes
-    assert abs(bench.put_bytes(0.5, 1) - (1.00002 * 192 + 9)) < 1e-9
+    """A put round reads its bucket's 128-byte lines and performs one 4-byte
+    CAS (8 bytes for 64-bit slots); plus an 8-byte key word and a result byte.
+    At load 0.9 (1.05175 rounds per put, one-line compact buckets) that is
+    147.83 bytes per put; a find reads its probed buckets, key and result."""
+    assert abs(bench.put_bytes(0.9, 1) - (1.05175 * (128 + 4) + 9)) < 1e-9
+    assert abs(bench.put_bytes(0.9, 1) - 147.831) < 1e-3
+    assert abs(bench.put_bytes(0.9, 2, 8) - (1.05175 * (256 + 8) + 9)) < 1e-9
     assert abs(bench.find_bytes(0.9, 2) - (1.22454 * 256 + 9)) < 1e-9
+    # the sector model charges the 64-byte write-back instead of the 4-byte atomic
+    assert abs(bench.put_bytes_sector(0.5, 1) - (1.00002 * 192 + 9)) < 1e-9
+
+
+def test_roofline_fraction_reproduces_from_the_profile():
+    """frac = algorithmic bytes of the put launch / its average duration / 8 TB/s.
+    With the rocprofv3 average of the put kernel at the headline shape
+    (profiles/cuckoo_c2_kernel_stats.md: 5.4415 ms for 120,795,955 keys)
+    that is 0.41."""
+    n = int(0.9 * (1 << 27))
+    assert n == 120795955
+    gbs = n * bench.put_bytes(0.9, 1) / 5.4415e-3 / 1e9
+    assert abs(gbs / bench.HBM_PEAK_GBS - 0.41) < 0.005
 
 
 def test_traffic_is_tied_to_kernel_sources():

@@ -104,6 +104,57 @@ def test_c3_iceberg_full_size_batches(gpu):
     assert false_hits == 0
 
 
+def test_c3_iceberg_mixed_stream_full_size(gpu):
+    """The dynamic-operation stream the benchmark times, batch for batch:
+    2^28 + 2^25 slots (16/32-bit, 34-bit keys), mixed batches of 2^20
+    operations (half find-or-puts with 30 % repeats, half finds with 50 %
+    hits) from load 0 to 0.9, one launch per batch in order on one stream.
+    The truth comes from the index each key was drawn from (keys = phi(index)):
+    for every distinct inserted key, exactly one PUT, in the first batch that
+    inserts it; a find answers 1 if an earlier batch inserted its key, 0 if no
+    batch up to its own did (either way if its own batch does); the count is
+    the number of distinct inserted keys, all of which are found afterwards."""
+    w, L0 = 34, 28
+    cap = (1 << L0) + (1 << (L0 - 3))
+    keys, ops, idx, n_fresh = synth.mixed_batches(w, 0xC2C2C2C2 + 3, cap, 0.9, 1 << 20, device=gpu)
+    nb, batch = keys.shape
+    t = cpht.Table(scheme=cpht.ICEBERG, key_bits=w, log2_slots0=L0, log2_slots1=L0 - 3, bucket0=32, bucket1=16,
+                   slot_bits0=16, slot_bits1=32, seed=9)
+    out = torch.empty(nb, batch, dtype=torch.uint8, device=gpu)
+    for b in range(nb):
+        t.mixed(keys[b], ops[b], out[b])
+    torch.cuda.synchronize()
+    print(f"mixed stream: {nb} batches, {n_fresh} distinct keys inserted", flush=True)
+    ins = ops == 1
+    # batch of each operation, and the first batch inserting each key index
+    bat = torch.arange(nb, device=gpu).repeat_interleave(batch).view(nb, batch)
+    ji, bi, oi = idx[ins], bat[ins], out[ins]
+    assert int(ji.max().item()) < n_fresh
+    first = torch.full((n_fresh,), nb, dtype=torch.int64, device=gpu).scatter_reduce(0, ji, bi, reduce="amin")
+    assert _count((oi != cpht.PUT) & (oi != cpht.FOUND)) == 0, "an insert answered neither PUT nor FOUND"
+    put = oi == cpht.PUT
+    assert _count(put) == n_fresh
+    puts_per_key = torch.bincount(ji[put], minlength=n_fresh)
+    assert _count(puts_per_key != 1) == 0, "a key was not answered PUT exactly once"
+    assert _count(first[ji[put]] != bi[put]) == 0, "a PUT came after the first batch inserting its key"
+    del ji, bi, oi, put, puts_per_key
+    jf, bf, of = idx[~ins], bat[~ins], out[~ins]
+    known = jf < n_fresh  # misses are phi(2^33 + j), never inserted
+    fb = torch.where(known, first[jf.clamp(max=n_fresh - 1)], torch.full_like(jf, nb))
+    before, same = fb < bf, fb == bf
+    assert _count(before & (of != 1)) == 0, "a key inserted by an earlier batch was not found"
+    assert _count(~before & ~same & (of != 0)) == 0, "a find answered 1 for a key not inserted yet"
+    assert _count(same & (of > 1)) == 0
+    del jf, bf, of, fb, before, same, bat
+    assert t.count()[0] == n_fresh
+    for a in range(0, n_fresh, 1 << 26):
+        k = synth.distinct_keys(w, 0xC2C2C2C2 + 3, a, min(1 << 26, n_fresh - a), device=gpu)
+        missed = _count(t.find(k) != 1)
+        assert missed == 0, f"{missed} inserted keys not found"
+    miss = synth.distinct_keys(w, 0xC2C2C2C2 + 3, synth.MISS_BASE, 1 << 24, device=gpu)
+    assert _count(t.find(miss) != 0) == 0
+
+
 def test_c5_table_shape_full_size(gpu):
     """The serving table: 2^32 + 2^29 slots (16/32-bit, 40-bit keys), bulk
     filled to load 0.5 in chunks; count and sampled finds are exact."""
