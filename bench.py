@@ -138,6 +138,8 @@ class Runner:
 # picked with --only).
 SECTIONS = ("plain", "equal", "window", "sweep", "small", "iceberg", "fop", "delete", "level3", "map", "many",
             "serving", "ceilings", "cpu")
+# Sections run only when named in --only (minutes of host time).
+OPT_IN = ("cpu_full",)
 
 # (slot bits, compact, slots per bucket) of the load sweep: compact 32-bit and
 # plain 64-bit slots at 8, 16 and 32 slots per bucket.
@@ -471,6 +473,79 @@ def cpu_baseline(log2_slots: int = 26):
         "host_cpu": _host_cpu(),
         "small_cuckoo": small,
         "iceberg_sample": ice,
+    }
+
+
+def cpu_full(torch, synth, dev, sweep=(0.5, 0.7, 0.8, 0.9, 0.95), batch=1 << 20):
+    """The sequential oracle at full scale, timed once on one host thread
+    (minutes of host time, so only on request):
+      - the compact cuckoo benchmark table (2^27 slots, 32 x 32-bit buckets,
+        37-bit keys) built from empty through every load of the sweep, the
+        time to each load being the build's time up to it (the oracle is
+        sequential, so this equals a separate build to that load), with 2^26
+        finds at 50 % hit timed at each load;
+      - the uniform dynamic-operation stream of the iceberg benchmark (2^28 +
+        2^25 slots, 16/32-bit, 34-bit keys; the same batches as the GPU run)
+        from load 0 to 0.9, batch by batch through the oracle's mixed call.
+    Keys are generated on the device and copied to host memory outside the
+    timed calls."""
+    import numpy as np
+
+    import oracle
+
+    t_all = time.perf_counter()
+    ck = oracle.Table(oracle.CUCKOO, W_KEY, LOG2_SLOTS, BUCKET, 32, seed=1)
+    n_max = int(max(sweep) * (1 << LOG2_SLOTS))
+    keys = synth.distinct_keys(W_KEY, KEY_SEED, 0, n_max, device=dev).cpu().numpy().astype(np.uint64)
+    built, build_s, rows = 0, 0.0, {}
+    for L in sweep:
+        n = int(L * (1 << LOG2_SLOTS))
+        a = time.perf_counter()
+        out = ck.insert(keys[built:n])
+        build_s += time.perf_counter() - a
+        assert (out == oracle.PUT).all(), f"oracle cuckoo build failed below load {L}"
+        built = n
+        q = synth.find_queries(W_KEY, KEY_SEED, n, N_FIND, 0.5, Q_SEED, device=dev).cpu().numpy().astype(np.uint64)
+        a = time.perf_counter()
+        f = ck.find(q)
+        fs = time.perf_counter() - a
+        rows[str(L)] = {"inserts": n, "insert_s": round(build_s, 2), "insert_mops": round(n / build_s / 1e6, 3),
+                        "finds": int(q.size), "find_s": round(fs, 2), "find_mops": round(q.size / fs / 1e6, 3),
+                        "hit_fraction": round(float(f.mean()), 4)}
+        print(f"[bench] cpu_full cuckoo load {L}: {rows[str(L)]}", file=sys.stderr, flush=True)
+    del ck, keys
+    w = 34
+    L0, L1 = LOG2_SLOTS + 1, LOG2_SLOTS - 2
+    cap = (1 << L0) + (1 << L1)
+    mk, mo, _, n_fresh = synth.mixed_batches(w, KEY_SEED + 3, cap, LOAD, batch, device=dev)
+    nb = mk.shape[0]
+    ice = oracle.Table(oracle.ICEBERG, w, L0, 32, 16, log2_slots1=L1, B1=16, s1=32, seed=9)
+    ms, nops, nfull = 0.0, 0, 0
+    for b in range(nb):
+        hk = mk[b].cpu().numpy().astype(np.uint64)
+        ho = mo[b].cpu().numpy()
+        a = time.perf_counter()
+        out = ice.mixed(hk, ho)
+        ms += (time.perf_counter() - a) * 1e3
+        nops += hk.size
+        nfull += int((out[ho == 1] == oracle.FULL).sum())
+        if b % 100 == 99:
+            print(f"[bench] cpu_full iceberg batch {b + 1}/{nb}: {nops / ms / 1e3:.2f} Mops/s", file=sys.stderr,
+                  flush=True)
+    occ, capo = ice.occupied(), ice.capacity()
+    del mk, mo, ice
+    return {
+        "kind": "oracle", "cores": 1, "host_threads_available": os.cpu_count(), "host_cpu": _host_cpu(),
+        "cuckoo_load_sweep": rows,
+        "cuckoo_shape": (f"compact cuckoo 2^{LOG2_SLOTS} slots, 32 x 32-bit buckets, {W_KEY}-bit keys; one build "
+                         f"from empty, timed to each load; {N_FIND} finds (50% hit) at each load"),
+        "iceberg_uniform_stream": {"ops": nops, "batches": nb, "ms": round(ms, 1),
+                                   "mops": round(nops / ms / 1e3, 3), "full": nfull,
+                                   "fill_factor": round(occ / capo, 4), "distinct_inserted": n_fresh,
+                                   "count_matches": occ == n_fresh},
+        "iceberg_shape": (f"iceberg 2^{L0} + 2^{L1} slots, B0=32 x 16-bit, B1=16 x 32-bit, {w}-bit keys; "
+                          f"{nb} mixed batches of {batch} ops (the GPU run's batches), load 0 -> {LOAD}"),
+        "seconds": round(time.perf_counter() - t_all, 1),
     }
 
 
@@ -1148,21 +1223,24 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop section")
     ap.add_argument("--only", default="",
                     help="comma list of extra sections to run beside the headline step, all others skipped "
-                         "('headline' for none): " + ",".join(SECTIONS))
+                         "('headline' for none): " + ",".join(SECTIONS + OPT_IN) +
+                         "; the OPT_IN sections (" + ",".join(OPT_IN) + ") run only when named here")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.only:
         want = set(args.only.split(",")) - {"headline"}  # "headline": the headline step alone
-        unknown = want - set(SECTIONS)
+        unknown = want - set(SECTIONS) - set(OPT_IN)
         if unknown:
             ap.error(f"unknown sections {sorted(unknown)}")
-        for sec in SECTIONS:
+        for sec in SECTIONS + OPT_IN:
             setattr(args, "no_" + sec, sec not in want)
     else:
         for sec in SECTIONS:
             if not hasattr(args, "no_" + sec):
                 setattr(args, "no_" + sec, False)
+        for sec in OPT_IN:
+            setattr(args, "no_" + sec, True)
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path has no multi-GPU "
@@ -1378,6 +1456,8 @@ def main():
 
     if not args.no_cpu:
         run_section(res, "cpu_baseline", cpu_baseline)
+    if not args.no_cpu_full:
+        run_section(res, "cpu_full", lambda: cpu_full(torch, synth, dev))
     print(json.dumps(res))
 
 

@@ -11,8 +11,9 @@ steps.  An operation carries a key k with hash index j and round counter c:
   slot, once written, is never EMPTY again, so staleness can only hide an
   occupant);
 * if some slot read EMPTY and is not in the operation's known-occupied mask,
-  it claims the first such slot with one compare-and-swap; a lost claim adds
-  the slot to the mask and uses up the round;
+  it claims the first such slot (with claim_any: any such slot, every choice
+  explored) with one compare-and-swap; a lost claim adds the slot to the mask
+  and uses up the round;
 * otherwise (every slot occupied) it swaps (r_j(k), j) into a victim row with
   one atomic exchange; the evicted word (r', j') together with the bucket
   address decodes, under permutation j', to the key k' that the operation
@@ -57,6 +58,10 @@ class CuckooScenario:
     prefill_tags: dict = field(default_factory=dict)  # slot index -> tag j of the pre-filled key
     stale_reads: bool = True
     expect_no_full: bool = False  # the table has room and C is large enough: every put must succeed
+    # claim any free slot of the snapshot (every choice explored) instead of
+    # the first: Alg. 4 asks only for some empty slot, and the kernel spreads
+    # the claims of keys that contend for one bucket over its empty slots
+    claim_any: bool = False
     # planted mistakes (the checker must reject them)
     bug_decode_with_carried_j: bool = False  # decode the evicted word with the carried key's j
     bug_no_known: bool = False               # forget lost claims
@@ -137,7 +142,8 @@ class CuckooChecker:
                 else:
                     free = [y for y in range(sc.B) if s2[y] and not (known >> y) & 1]
                     if free:
-                        out.append(th((("claim", free[0]), k, j, c, known, (), None)))
+                        for q in (free if sc.claim_any else free[:1]):
+                            out.append(th((("claim", q), k, j, c, known, (), None)))
                     else:
                         out.append(th((("evict",), k, j, c, known, (), None)))
             return out

@@ -3,7 +3,8 @@ the kernel's step granularity, on tiny tables: per-slot snapshot reads that
 may be stale, CAS claims with known-occupied masks, eviction swaps whose
 evicted word is decoded under its own hash index, victims in every row.  No
 key is lost or stored twice, the early-exit invariant of the lookup holds,
-every put succeeds where there is room, and the planted mistakes are caught:
+every put succeeds where there is room (also when a claim takes any free
+slot of the snapshot, not the first), and the planted mistakes are caught:
 decoding the evicted word with the carried key's hash index, and forgetting
 lost claims (which lets a stale line be claimed again and again)."""
 import pytest
@@ -53,6 +54,32 @@ def test_cuckoo_put_interleavings_are_correct(make):
     ok, errors, states, terminal = check(make())
     assert ok, errors
     assert terminal > 0
+
+
+@pytest.mark.parametrize("make", [contention, evictions, over_capacity, stale_prefill])
+def test_cuckoo_put_claiming_any_free_slot_is_correct(make):
+    """Claims spread over the snapshot's free slots (every choice explored):
+    holes may remain in a bucket, and still no key is lost or stored twice,
+    the lookup's early-exit invariant holds and no put fails with room."""
+    ok, errors, states, terminal = check(make(claim_any=True))
+    assert ok, errors
+    assert terminal > 0
+
+
+def test_spread_claims_leave_holes_in_some_interleaving():
+    """With claims spread over free slots, some terminal table has an EMPTY
+    slot before an occupied one in a bucket (so the non-empty slots of a
+    cuckoo bucket need not form a prefix), which the lookup tolerates."""
+    from oracle.interleave_cuckoo import CuckooChecker
+
+    keys = {"k1": ((0, 1), (1, 1))}
+    c = CuckooChecker(CuckooScenario(B=2, n_buckets=2, H=2, C=4, keys=keys, ops=["k1"], claim_any=True,
+                                     expect_no_full=True))
+    terminals = []
+    orig = c._check_terminal
+    c._check_terminal = lambda st: (terminals.append(st[0]), orig(st))
+    assert c.run() and not c.errors
+    assert any(tb[0] is None and tb[1] is not None for tb in terminals)
 
 
 def test_evictions_really_happen_in_the_scenarios():
