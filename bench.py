@@ -136,7 +136,7 @@ class Runner:
 
 # Optional sections of the JSON line (each has a --no-<name> switch or is
 # picked with --only).
-SECTIONS = ("plain", "equal", "window", "sweep", "small", "iceberg", "fop", "delete", "level3", "map", "many",
+SECTIONS = ("plain", "equal", "cachefree", "window", "sweep", "small", "iceberg", "fop", "delete", "level3", "map", "many",
             "serving", "ceilings", "cpu")
 # Sections run only when named in --only (minutes of host time).
 OPT_IN = ("cpu_full",)
@@ -165,6 +165,53 @@ def equal_memory(torch, cpht, keys, queries, n_ins, reps=5):
            "find_mops": round(N_FIND / (sum(fnd) / len(fnd) / 1000.0) / 1e6, 1)}
     del t, r
     return res
+
+
+def cache_free(torch, cpht, synth, dev, reps=3):
+    """The headline step on tables far larger than the 256 MB Infinity Cache,
+    so that bucket reads come from HBM: compact 2^30 x 32-bit slots and plain
+    2^29 x 64-bit slots (4 GiB each), plus compact 2^29 (the plain table's
+    slot count, 2 GiB), each built to load 0.9 with a new permutation seed
+    per repetition, then 2^26 finds at 50 % hit."""
+    rows = []
+    for label, log2_slots, slot_bits, cmp_ in (("compact_4GiB", 30, 32, 1), ("plain_4GiB", 29, 64, 0),
+                                               ("compact_2GiB", 29, 32, 1)):
+        n = int(LOAD * (1 << log2_slots))
+        keys = synth.distinct_keys(W_KEY, KEY_SEED, 0, n, device=dev)
+        queries = synth.find_queries(W_KEY, KEY_SEED, n, N_FIND, 0.5, Q_SEED, device=dev)
+        t = cpht.Table(scheme=cpht.CUCKOO, key_bits=W_KEY, log2_slots0=log2_slots, bucket0=BUCKET,
+                       slot_bits0=slot_bits, n_hash=2, max_chain=256, compact=cmp_, seed=1)
+        r = Runner(torch, cpht, t, keys, queries, n)
+        for rep in range(reps + 1):
+            r.step(seed=700 + rep, record=rep > 0)
+        ins, fnd = r.times_ms()
+        n_put = int((r.out == cpht.PUT).sum().item())
+        hit = float(r.found.float().mean().item())
+        occ, _ = t.count()
+        ok = n_put == n and occ == n and abs(hit - 0.5) < 0.01
+        ims, fms = sum(ins) / len(ins), sum(fnd) / len(fnd)
+        lines = 1 if slot_bits == 32 else 2
+        put_gbs = n * put_bytes(LOAD, lines, 4 if slot_bits == 32 else 8) / (ims / 1000.0) / 1e9
+        find_gbs = N_FIND * find_bytes(LOAD, lines) / (fms / 1000.0) / 1e9
+        rows.append({"table": label, "slots": 1 << log2_slots, "slot_bits": slot_bits, "compact": bool(cmp_),
+                     "table_bytes": t.level_bytes(0), "inserts": n, "check": "ok" if ok else "FAILED",
+                     "insert_mops": round(n / (ims / 1000.0) / 1e6, 1),
+                     "find_mops": round(N_FIND / (fms / 1000.0) / 1e6, 1),
+                     "insert_ms": round(ims, 3), "find_ms": round(fms, 3),
+                     "put_hbm_frac": round(put_gbs / HBM_PEAK_GBS, 4),
+                     "find_hbm_frac": round(find_gbs / HBM_PEAK_GBS, 4),
+                     "find_line_reads_G_per_s": round(N_FIND * PROBES_PER_FIND[LOAD] * lines / (fms / 1000.0) / 1e9,
+                                                      2)})
+        del t, r, keys, queries
+        torch.cuda.empty_cache()
+    by = {r["table"]: r for r in rows}
+    c, p = by["compact_4GiB"], by["plain_4GiB"]
+    return {"rows": rows,
+            "compact_vs_plain_equal_memory": {"insert": round(c["insert_mops"] / p["insert_mops"], 3),
+                                              "find": round(c["find_mops"] / p["find_mops"], 3)},
+            "compact_vs_plain_equal_slots": {
+                "insert": round(by["compact_2GiB"]["insert_mops"] / p["insert_mops"], 3),
+                "find": round(by["compact_2GiB"]["find_mops"] / p["find_mops"], 3)}}
 
 
 def marginal_window(torch, cpht, keys, n_ins, lo=0.85, reps=5):
@@ -1006,13 +1053,13 @@ def serving(torch, cpht, synth, dev, n_req=100000, n_req_other=20000, log2_slots
     # cut the trace where its inserts would pass stop_load
     ins_upto = torch.cumsum(is_ins.to(torch.int64), 0)
     room = int(stop_load * cap) - n_pre
-    over = torch.nonzero(ins_upto > room)
-    if over.numel():
-        last_op = int(over[0].item())
+    # first operation past the room (the running count is sorted)
+    last_op = int(torch.searchsorted(ins_upto, torch.tensor([room], device=dev), right=True)[0].item())
+    if last_op < total:
         n_req = int(np.searchsorted(offsets, last_op, side="right")) - 1
         total = int(offsets[n_req])
         is_ins = is_ins[:total]
-    del ins_upto, over
+    del ins_upto
     n_req_other = min(n_req_other, n_req)
     is_hit = synth.uniform_below(0x32, total, 2, dev) == 1
     fresh_idx = n_pre + torch.cumsum(is_ins.to(torch.int64), 0)
@@ -1166,6 +1213,15 @@ def ceilings(torch, cpht, dev, res, split_keys):
     out["find_vs_line_reads"] = round(res["find_mops"] * lines_find / (r["line_reads"]["G_per_s"] * 1e3), 3)
     out["find_vs_line_reads_4GiB"] = round(res["find_mops"] * lines_find /
                                            (out["4GiB"]["line_reads"]["G_per_s"] * 1e3), 3)
+    cf = res.get("cache_free")
+    if isinstance(cf, dict) and "rows" in cf:
+        # the 4 GiB compact table (not cache-resident) against the 4 GiB ceilings
+        c4 = next(row for row in cf["rows"] if row["table"] == "compact_4GiB")
+        g = out["4GiB"]
+        out["cache_free_find_vs_line_reads_4GiB"] = round(c4["find_line_reads_G_per_s"] /
+                                                          g["line_reads"]["G_per_s"], 3)
+        out["cache_free_put_vs_line_read_then_cas_4GiB"] = round(
+            c4["insert_mops"] * lines_put / (g["line_read_then_cas"]["G_per_s"] * 1e3), 3)
     # the quotienting split alone (three permutations per key) on the
     # benchmark's keys, against the build that applies it
     keys = split_keys[: 1 << 26]  # a power-of-two buffer of the benchmark's keys
@@ -1384,6 +1440,9 @@ def main():
 
     if not args.no_plain and not args.no_equal:
         run_section(res, "equal_memory", lambda: equal_memory(torch, cpht, keys, queries, n_ins))
+
+    if not args.no_cachefree:
+        run_section(res, "cache_free", lambda: cache_free(torch, cpht, synth, dev))
 
     if not args.no_window:
         run_section(res, "marginal_window", lambda: marginal_window(torch, cpht, keys, n_ins))
