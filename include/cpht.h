@@ -235,6 +235,20 @@ cpht_status_t cpht_sorted_fop(cpht_table_t t, const void* d_keys, uint64_t n, ui
  * bytes per key with 64-bit key words, 28 with 32-bit ones). */
 cpht_status_t cpht_sorted_fop_workspace(cpht_table_t t, uint64_t n, uint64_t* bytes);
 
+/* For callers that cannot allocate device memory (code under stream or graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * find-or-put as cpht_sorted_fop, with the same answers, but its scratch is a
+ * fixed 40 MiB array of device memory that the library holds on each GPU it
+ * runs on until the process ends (its address is looked up once per device,
+ * on the first call there).  The call allocates nothing and takes no
+ * workspace.  n <= 2^20 keys (CPHT_E_ARG above that; CPHT_E_STATE on an
+ * iceberg table).  All calls on one GPU share that GPU's array: calls that
+ * overlap on one GPU (other streams, other threads, other tables) race and
+ * give undefined answers; order them on one stream or synchronise between
+ * them.  The array keeps the last call's contents; no step of the pipeline
+ * relies on its previous contents. */
+cpht_status_t cpht_sorted_fop_noalloc(cpht_table_t t, const void* d_keys, uint64_t n, uint8_t* d_out, void* stream);
+
 /* Slots holding a key (tombstones excluded; third-level slots included) and
  * total slots of the bucket levels (fill factor = occupied / capacity,
  * Sec. 2.1; with a third level it can exceed 1).  Synchronises `stream`. */

@@ -83,6 +83,7 @@ _SIGNATURES = {
     "cpht_import": (_I32, [_VP, _U32, _VP, _U64]),
     "cpht_sorted_fop": (_I32, [_VP, _VP, _U64, _VP, _VP, _U64, _VP]),
     "cpht_sorted_fop_workspace": (_I32, [_VP, _U64, ctypes.POINTER(_U64)]),
+    "cpht_sorted_fop_noalloc": (_I32, [_VP, _VP, _U64, _VP, _VP]),
     "cpht_count": (_I32, [_VP, ctypes.POINTER(_U64), ctypes.POINTER(_U64), _VP]),
     "cpht_level_bytes": (_I32, [_VP, _U32, ctypes.POINTER(_U64)]),
     "cpht_level3_used": (_I32, [_VP, ctypes.POINTER(_U32)]),
@@ -396,6 +397,17 @@ class Table:
         _check(lib().cpht_sorted_fop(self._h, self._keys(keys), n, _dev_ptr(out, "out"),
                                      _dev_ptr(workspace, "workspace"), workspace.numel(), _stream(stream)),
                "cpht_sorted_fop")
+        return out
+
+    def sorted_fop_noalloc(self, keys: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+        """sorted_fop without a workspace: the library's fixed per-GPU scratch
+        is used and nothing is allocated (n <= 2^20; `out` is required)."""
+        n = keys.numel()
+        if out is None:
+            raise ValueError("out is required (the call allocates nothing)")
+        out = self._out(out, n, keys)
+        _check(lib().cpht_sorted_fop_noalloc(self._h, self._keys(keys), n, _dev_ptr(out, "out"), _stream(stream)),
+               "cpht_sorted_fop_noalloc")
         return out
 
     def split(self, perm_index: int, keys: torch.Tensor, stream=None):

@@ -451,6 +451,17 @@ cpht_status_t cpht_export_values(cpht_table_t t, uint32_t level, void* h_dst, ui
   return device_status(e);
 }
 
+// The sorted find-or-put on t's device (current) with workspace `ws`.
+static cpht_status_t run_sorted_fop(cpht_table_t t, const void* d_keys, uint64_t n, uint8_t* d_out, void* ws,
+                                    void* stream) {
+  int cus = 0;
+  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, t->device);
+  if (e != hipSuccess) return device_status(e);
+  e = launch_sorted_fop(t->tk, t->ck, (int)t->cfg.key_bits, d_keys, n, d_out, ws,
+                        (uint32_t)(cus > 0 ? cus * 8 : 2048), as_stream(stream));
+  return device_status(e);
+}
+
 cpht_status_t cpht_sorted_fop_workspace(cpht_table_t t, uint64_t n, uint64_t* bytes) {
   if (!t || !bytes) return CPHT_E_ARG;
   if (!t->ck) return CPHT_E_STATE;
@@ -469,12 +480,21 @@ cpht_status_t cpht_sorted_fop(cpht_table_t t, const void* d_keys, uint64_t n, ui
   if (workspace_bytes < sorted_fop_workspace(n, t->cfg.key_bits > 32 ? 8 : 4)) return CPHT_E_ARG;
   DeviceGuard g(t->device);
   if (!g.ok) return CPHT_E_DEVICE;
-  int cus = 0;
-  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, t->device);
+  return run_sorted_fop(t, d_keys, n, d_out, d_workspace, stream);
+}
+
+cpht_status_t cpht_sorted_fop_noalloc(cpht_table_t t, const void* d_keys, uint64_t n, uint8_t* d_out, void* stream) {
+  if (!t) return CPHT_E_ARG;
+  if (!t->ck) return CPHT_E_STATE;
+  if (n == 0) return CPHT_OK;
+  if (!d_keys || !d_out || n > NOALLOC_MAX_KEYS) return CPHT_E_ARG;
+  if (sorted_fop_workspace(n, t->cfg.key_bits > 32 ? 8 : 4) > NOALLOC_SCRATCH_BYTES) return CPHT_E_ARG;
+  DeviceGuard g(t->device);
+  if (!g.ok) return CPHT_E_DEVICE;
+  void* ws = nullptr;
+  const hipError_t e = sorted_fop_scratch(t->device, &ws);
   if (e != hipSuccess) return device_status(e);
-  e = launch_sorted_fop(t->tk, t->ck, (int)t->cfg.key_bits, d_keys, n, d_out, d_workspace,
-                        (uint32_t)(cus > 0 ? cus * 8 : 2048), as_stream(stream));
-  return device_status(e);
+  return run_sorted_fop(t, d_keys, n, d_out, ws, stream);
 }
 
 cpht_status_t cpht_count(cpht_table_t t, uint64_t* occupied, uint64_t* capacity, void* stream) {

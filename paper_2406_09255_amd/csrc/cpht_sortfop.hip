@@ -27,6 +27,14 @@
 #include "cpht_sortfop.hpp"
 
 #include <algorithm>
+#include <mutex>
+
+// Device scratch of the allocation-free variant of the pipeline: one copy of
+// this array per GPU, loaded with the library's code and kept until the
+// process ends.  Host code never passes the array's name to a kernel (on the
+// host it is only a stand-in for the symbol); it uses the per-device address
+// that sorted_fop_scratch() obtains from the runtime.
+static __device__ __align__(256) uint8_t scratch[cpht::NOALLOC_SCRATCH_BYTES];
 
 namespace cpht {
 namespace {
@@ -598,6 +606,23 @@ hipError_t run(const TableK& T, const CkVariant* v, int key_bits, const K* keys,
 }  // namespace
 
 uint64_t sorted_fop_workspace(uint64_t n, int key_bytes) { return layout(n, key_bytes).total; }
+
+hipError_t sorted_fop_scratch(int device, void** ptr) {
+  constexpr int MAX_DEVICES = 64;
+  static std::mutex mu;
+  static void* addr[MAX_DEVICES] = {};
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[device] = p;
+  }
+  *ptr = addr[device];
+  return hipSuccess;
+}
 
 hipError_t launch_sorted_fop(const TableK& T, const CkVariant* v, int key_bits, const void* keys, uint64_t n,
                              uint8_t* out, void* workspace, uint32_t blocks, hipStream_t s) {
