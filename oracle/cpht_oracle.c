@@ -36,7 +36,8 @@
  *      secondary buckets are full.
  *   7. A table checker for raw table images (well-formedness and the order
  *      property of Appendix A Definition 2, no duplicates (Lemma 1), prefix
- *      filling, and the cuckoo early-exit invariant of Sec. 2.2 / 4.4).
+ *      filling of iceberg buckets, and the cuckoo early-exit invariant of
+ *      Sec. 2.2 / 4.4).
  *
  * Raw table image layout (shared contract with the GPU library, documented in
  * the public header): level x is an array of 2^nb_x buckets of B_x slots of
@@ -798,8 +799,11 @@ static int cmp_u64(const void* a, const void* b)
  *   - every slot is EMPTY, a tombstone, or a valid stored form: occupancy
  *     bit set, unused high bits clear, tag in range (Definition 2, first
  *     item);
- *   - the non-empty slots of every bucket form a prefix (inserts always take
- *     the first empty slot, Alg. 1/2/4; the cuckoo lookup relies on it);
+ *   - iceberg: the non-empty slots of every bucket form a prefix (the
+ *     find-or-put takes the first empty slot, Alg. 1/2; the order property
+ *     of Definition 2 needs it).  Not for cuckoo: the put of Alg. 4 may take
+ *     any empty slot, and its lookup asks only whether a bucket holds the key
+ *     and whether it has an empty slot (Sec. 4.4, Lookup);
  *   - for a non-compact table the stored pi_j(k) addresses its own bucket;
  *   - no key is stored twice (Lemma 1);
  *   - iceberg: the order property of Definition 2 for every stored key;
@@ -833,7 +837,8 @@ int or_check3(const or_cfg_t* c, const void* img0, const void* img1, const void*
             for (uint32_t y = 0; y < L->B; ++y) {
                 uint64_t v = bk[y];
                 if (v == 0) { seen_empty = 1; continue; }
-                if (seen_empty) FAIL("level %d bucket %llu: slot %u filled after an empty slot", x, (unsigned long long)b, y);
+                if (seen_empty && c->scheme != OR_CUCKOO)
+                    FAIL("level %d bucket %llu: slot %u filled after an empty slot", x, (unsigned long long)b, y);
                 if (v == OR_TOMB) continue;
                 if (!(v >> (L->s - 1) & 1)) FAIL("level %d bucket %llu slot %u: occupancy bit clear", x, (unsigned long long)b, y);
                 if (used < (uint64_t)L->s - 1 && (v & ~(1ULL << (L->s - 1))) >> used)

@@ -41,9 +41,14 @@ enum : int { CK_FIND = 0, CK_PUT = 1, CK_ERASE = 2 };
 //     to hash j+1 out of a full bucket, so k cannot be further on; tombstones
 //     count as occupied, so deletes keep this true).
 //   CK_PUT: Alg. 4.  Per round, the bucket T[a_j(k)] of the carried key k is
-//     snapshotted; with an empty slot, the first one is claimed with CAS (a
+//     snapshotted; with an empty slot, one is claimed with CAS: the first
+//     empty slot at or after a start slot drawn from (k, round), else the
+//     first empty slot (Alg. 4 asks for some empty slot; spreading the claims
+//     of keys that share a bucket lets several of them win in one round).  A
 //     lost claim uses up the round and marks the slot known-occupied, so a
-//     stale re-read cannot offer it again); with no empty slot, the victim row
+//     stale re-read cannot offer it again.  Buckets therefore need not fill as
+//     a prefix, which the lookup does not rely on: it asks whether the bucket
+//     holds the key and whether any slot is empty.  With no empty slot, the victim row
 //     chosen from (k, round) is swapped with (r_j(k), j) and the evicted pair
 //     (r', j') continues as key pi_{j'}^{-1}(a . r') with hash index j'+1 mod
 //     H; a tombstone as victim ends the chain (nothing is carried).  After C
@@ -72,18 +77,25 @@ __device__ __forceinline__ void cuckoo_body(const TableK& T, const BatchK& Bt, u
   while (__ballot(pend) != 0ull) {
     bool claim = false, evict = false, erase = false;
     uint32_t q = 0;
+    uint32_t start = 0;  // first slot the claim of this round looks at
+    if constexpr (PUT) start = claim_start((uint64_t)k, c, (uint32_t)B);
 #pragma unroll 1
     for (int t0 = 0; t0 < G; t0 += D) {
       uint32_t buf[D][W];
       uint64_t ev[D];
       KM kn[D];
+      uint32_t p0[D];
       bool live[D];
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         live[d] = st.bcast_bool(pend, t0 + d);
         const uint32_t a = st.bcast((uint32_t)s.a, t0 + d);
-        if constexpr (!PUT) ev[d] = st.template bcast_slot<S>(s.e, t0 + d);
-        else kn[d] = st.bcast_mask(known, t0 + d);
+        if constexpr (!PUT) {
+          ev[d] = st.template bcast_slot<S>(s.e, t0 + d);
+        } else {
+          kn[d] = st.bcast_mask(known, t0 + d);
+          p0[d] = st.bcast(start, t0 + d);
+        }
         if (live[d]) load_words<W>(buf[d], L.base + (uint64_t)a * L.bucket_words + (uint32_t)(st.rk * W));
       }
 #pragma unroll
@@ -106,11 +118,17 @@ __device__ __forceinline__ void cuckoo_body(const TableK& T, const BatchK& Bt, u
             pend = false;
           }
         } else {
-          const int le = lane_first_empty<S, W>(buf[d], lane_bits<PER>(kn[d], st.rk * PER));
-          const uint32_t em = st.ballot(le < PER);
+          const uint32_t kb = lane_bits<PER>(kn[d], st.rk * PER);
+          // this lane's slots that lie before the start slot
+          const int before = min(max((int)p0[d] - st.rk * PER, 0), PER);
+          const uint32_t skip = before >= 32 ? 0xFFFFFFFFu : ((1u << before) - 1u);
+          const int le_from = lane_first_empty<S, W>(buf[d], kb | skip);
+          const int le_any = lane_first_empty<S, W>(buf[d], kb);
+          const uint32_t em_from = st.ballot(le_from < PER);
+          const uint32_t em = st.ballot(le_any < PER);
           if (em) {
-            const int f = ctz32(em);
-            const uint32_t qq = (uint32_t)(f * PER) + st.bcast((uint32_t)le, f);
+            const int f = ctz32(em_from ? em_from : em);
+            const uint32_t qq = (uint32_t)(f * PER) + st.bcast((uint32_t)(em_from ? le_from : le_any), f);
             if (mine) { claim = true; q = qq; }
           } else if (mine) {
             evict = true;

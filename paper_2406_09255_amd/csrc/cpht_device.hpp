@@ -186,6 +186,14 @@ __device__ __forceinline__ uint32_t victim_row(uint64_t k, uint32_t c, uint32_t 
   return (uint32_t)(mix64((k ^ ((uint64_t)c << 32)) + 0x9E3779B97F4A7C15ull) & (B - 1));
 }
 
+// Slot at which the cuckoo put of carried key k starts looking for an empty
+// slot in round c: high bits of the same splitmix64 output.  Concurrent puts
+// aimed at one bucket then spread their claims over its empty slots instead
+// of all claiming the first one.
+__device__ __forceinline__ uint32_t claim_start(uint64_t k, uint32_t c, uint32_t B) {
+  return (uint32_t)(mix64((k ^ ((uint64_t)c << 32)) + 0x9E3779B97F4A7C15ull) >> 32) & (B - 1);
+}
+
 // ---------------------------------------------------------------------------
 // Lane-local slot views.  A lane holds W words = W*32/S slots; the slot index
 // within the lane is a compile-time constant wherever registers are indexed.

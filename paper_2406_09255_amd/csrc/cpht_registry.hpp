@@ -37,7 +37,8 @@ struct CkVariant {
   X(16, 16, 16, 2) X(16, 32, 16, 2) X(32, 32, 16, 2) X(32, 32, 16, 4) X(64, 64, 16, 4) X(64, 64, 16, 8) \
   X(16, 16, 32, 2) X(16, 16, 32, 4) X(16, 32, 32, 2) X(16, 32, 32, 4) X(32, 32, 32, 4) X(32, 32, 32, 8) \
   X(64, 64, 32, 8) X(64, 64, 32, 16) \
-  X(16, 16, 64, 4) X(16, 16, 64, 8) X(16, 32, 64, 4) X(16, 32, 64, 8) X(32, 32, 64, 8) X(32, 32, 64, 16) \
+  X(16, 16, 64, 4) X(16, 16, 64, 8) X(16, 32, 64, 4) X(16, 32, 64, 8) X(16, 32, 64, 2) X(32, 32, 64, 8) \
+  X(32, 32, 64, 16) \
   X(64, 64, 64, 16) X(64, 64, 64, 32)
 
 // Cuckoo variants: (S, B, G); first entry per (S, B) is the default, then the

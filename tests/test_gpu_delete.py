@@ -6,7 +6,8 @@ timing, so answers are compared per distinct key (exactly one 1 for a stored
 key, none for an absent one); everything after the batch is unique and is
 compared exactly: the decoded key set, every lookup, the occupied count, and
 the number of tombstones.  The checker accepts tombstones and still requires
-non-empty slots to form a prefix and the order / early-exit invariants.
+the non-empty slots of iceberg buckets to form a prefix, and the order /
+early-exit invariants.
 """
 from __future__ import annotations
 

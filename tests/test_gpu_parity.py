@@ -372,7 +372,13 @@ def test_zero_bit_remainders(gpu):
     oc = oracle_table(c)
     assert (c.bulk_build(dk).cpu().numpy() == cpht.PUT).all()
     oc.insert(host_u64(keys))
-    assert np.array_equal(images(c)[0], oc.export(0))
+    # the bucket of every key is forced (one key per bucket, hash 0); the put
+    # may take any empty slot of it, so compare each bucket's one stored form
+    got = images(c)[0].view(np.uint32).reshape(-1, 32)
+    want = oc.export(0).view(np.uint32).reshape(-1, 32)
+    assert ((got != 0).sum(1) == 1).all() and ((want != 0).sum(1) == 1).all()
+    assert np.array_equal(got.max(1), want.max(1))
+    assert np.array_equal(check_table(c), np.arange(1 << w, dtype=np.uint64))
     assert (c.find(dk).cpu().numpy() == 1).all()
 
 

@@ -506,6 +506,26 @@ def test_checker_rejects_cuckoo_early_exit_violation():
     assert not ok
 
 
+def test_checker_accepts_cuckoo_bucket_with_holes():
+    """Alg. 4 claims some empty slot, not necessarily the first, so a cuckoo
+    bucket may have an empty slot before a filled one; the checker accepts
+    that (and the key set is unchanged), while the same hole in an iceberg
+    bucket is still rejected (test_checker_rejects_hole)."""
+    t = oracle.Table(oracle.CUCKOO, 20, 10, 8, 32, seed=7)
+    keys = _rng(13).choice(1 << 20, size=600, replace=False).astype(np.uint64)
+    t.insert(keys)
+    s0 = _slots(t.export(0))
+    ok, msg, want = oracle.check_images(t.cfg, s0.view(np.uint8))
+    assert ok, msg
+    rows = s0.reshape(-1, 8)
+    filled = (rows != 0).sum(1)
+    b = int(np.nonzero((filled >= 2) & (filled < 8))[0][0])
+    rows[b, 7], rows[b, 0] = rows[b, 0], 0  # slot 0 moves to the last (empty) slot
+    ok, msg, got = oracle.check_images(t.cfg, s0.view(np.uint8))
+    assert ok, msg
+    assert np.array_equal(np.sort(got), np.sort(want))
+
+
 def test_insert_outcome_checker_rejects_double_put():
     keys = np.array([5, 5, 6], np.uint64)
     assert sets.check_insert_outcomes(np.zeros(0, np.uint64), keys, np.array([1, 2, 1], np.uint8))[0]
