@@ -48,12 +48,12 @@ ICE_L2 = {"put": 0.075824, "find": 0.314262}
 KEY_BYTES = 8
 RESULT_BYTES = 1
 CAS_BYTES = 4  # the atomic of a put round moves one 32-bit slot (8 bytes for 64-bit slots)
-SECTOR = 64  # write-back unit of a modified slot (measured: 68.7 B written per put at 1.05 rounds)
+SECTOR = 64  # write-back unit of a modified slot (measured: 67.0 B written per put at 1.05 rounds)
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by the
 # copy-kernel calibration factors 2.0 / 1.0), profiles/cuckoo_c2_hbm_bytes.md.
 # Valid only for the kernel sources they were taken with (hash of KERNEL_SOURCES below).
-TRAFFIC = {"csrc_sha": "0d93f8ec9af4f898", "cuckoo_put": 25742989235, "cuckoo_find": 11034847358}
+TRAFFIC = {"csrc_sha": "9bd1d34100d51734", "cuckoo_put": 25333017600, "cuckoo_find": 11035480064}
 
 
 # The sources the profiled cuckoo kernels are compiled from.
@@ -62,7 +62,7 @@ KERNEL_SOURCES = ("cpht_device.hpp", "cpht_cuckoo.hpp", "cpht_registry.hpp", "in
 # Measured HBM bytes per operation (read + written, same calibration) of the
 # iceberg kernels at the iceberg_static shape, profiles/iceberg_hbm_bytes.md;
 # valid for the iceberg sources they were taken with.
-ICE_TRAFFIC = {"src_sha": "2e7aebae9bb76098", "insert_16_32": 222.6, "find_16_32": 214.3,
+ICE_TRAFFIC = {"src_sha": "7af84e15309d9e7a", "insert_16_32": 222.6, "find_16_32": 214.3,
                "insert_64_64": 350.9, "find_64_64": 344.0}
 ICE_SOURCES = ("cpht_device.hpp", "cpht_iceberg.hpp", "cpht_registry.hpp", "inst_iceberg_u64.hip")
 

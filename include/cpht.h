@@ -375,7 +375,9 @@ typedef struct cpht_server* cpht_server_t;
 typedef struct {
     uint32_t max_inflight;    /* concurrent launches (streams), 1..64 */
     uint32_t coalesce;        /* 1: pack several requests per launch; 0: one request per launch */
-    uint64_t staging_keys;    /* device staging capacity in keys (a request must fit it) */
+    uint64_t staging_keys;    /* device staging capacity in keys (a request must fit it); 0: sized at
+                                 start from the free device memory (a quarter of it, at most 2^28 keys;
+                                 CPHT_E_NOMEM if that is below max_batch_keys) */
     uint64_t max_batch_keys;  /* keys per launch when coalescing (<= staging_keys unless zero_copy) */
     uint32_t zero_copy;       /* 1: the device works on the pinned request buffers in place (no staging) */
     uint32_t pad;             /* must be 0 */

@@ -17,6 +17,7 @@
 // covers a run of queued requests that lie back to back in all three buffers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -388,15 +389,28 @@ cpht_status_t cpht_server_start(cpht_table_t t, const cpht_server_config_t* cfg,
   if (cfg->max_inflight < 1 || cfg->max_inflight > 64 || cfg->max_batch_keys < 1 || cfg->zero_copy > 1 ||
       cfg->pad != 0)
     return CPHT_E_ARG;
-  if (!cfg->zero_copy && (cfg->staging_keys < 1 || cfg->max_batch_keys > cfg->staging_keys)) return CPHT_E_ARG;
+  if (!cfg->zero_copy && cfg->staging_keys != 0 && cfg->max_batch_keys > cfg->staging_keys) return CPHT_E_ARG;
+  const uint64_t key_bytes = t->cfg.key_bits > 32 ? 8 : 4;
+  DeviceGuard g(t->device);
+  if (!g.ok) return CPHT_E_DEVICE;
+  uint64_t staging = cfg->staging_keys;
+  if (!cfg->zero_copy && staging == 0) {
+    // the ring is the admission budget: a quarter of the device memory free
+    // now (a key word, an opcode and a result byte per key), at most 2^28 keys
+    size_t free_b = 0, total_b = 0;
+    const hipError_t me = hipMemGetInfo(&free_b, &total_b);
+    if (me != hipSuccess) return device_status(me);
+    staging = std::min<uint64_t>((uint64_t)free_b / 4 / (key_bytes + 2), 1ull << 28);
+    if (staging < cfg->max_batch_keys) return CPHT_E_NOMEM;
+  }
   cpht_server* s = new (std::nothrow) cpht_server();
   if (!s) return CPHT_E_NOMEM;
   s->table = t;
   s->cfg = *cfg;
-  s->key_bytes = t->cfg.key_bits > 32 ? 8 : 4;
-  s->ring_cap = cfg->zero_copy ? 0 : cfg->staging_keys;
-  DeviceGuard g(t->device);
-  hipError_t e = g.ok ? hipSuccess : hipErrorInvalidDevice;
+  s->cfg.staging_keys = cfg->zero_copy ? cfg->staging_keys : staging;
+  s->key_bytes = key_bytes;
+  s->ring_cap = cfg->zero_copy ? 0 : staging;
+  hipError_t e = hipSuccess;
   if (!cfg->zero_copy) {  // the device staging ring
     if (e == hipSuccess) e = hipMalloc(&s->d_keys, s->ring_cap * s->key_bytes);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s->d_ops), s->ring_cap);

@@ -160,6 +160,24 @@ def test_server_admission_waits_for_staging(gpu):
         assert np.array_equal(res[f], want[f])
 
 
+def test_server_staging_sized_from_free_memory(gpu):
+    """staging_keys = 0: the ring (the admission budget) is sized at start
+    from the free device memory; requests are served as with a fixed ring."""
+    pre = 10000
+    reqs = _requests(30, pre, 5, pre)
+    t = _table(24)
+    S = _prefill(t, gpu, pre)
+    srv = cpht.Server(t, max_inflight=2, coalesce=1, staging_keys=0, max_batch_keys=1 << 16)
+    outs, _ = _run(srv, reqs)
+    srv.stop()
+    for (k, o), res in zip(reqs, outs):
+        hk, ho = host_u64(k), o.numpy()
+        want, S, _ = sets.mixed(S, hk, ho)
+        f = ho == 0
+        assert np.array_equal(res[f], want[f])
+        assert np.isin(res[~f], [cpht.PUT, cpht.FOUND]).all()
+
+
 @pytest.mark.parametrize("zero_copy", [0, 1])
 def test_server_trace_replay(gpu, zero_copy):
     pre = 30000
