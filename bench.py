@@ -136,7 +136,7 @@ class Runner:
 
 # Optional sections of the JSON line (each has a --no-<name> switch or is
 # picked with --only).
-SECTIONS = ("plain", "equal", "cachefree", "window", "sweep", "small", "iceberg", "fop", "delete", "level3", "map", "many",
+SECTIONS = ("plain", "equal", "cachefree", "window", "sweep", "servingsmall", "small", "iceberg", "fop", "delete", "level3", "map", "many",
             "serving", "ceilings", "cpu")
 # Sections run only when named in --only (minutes of host time).
 OPT_IN = ("cpu_full",)
@@ -1024,7 +1024,8 @@ def serving(torch, cpht, synth, dev, n_req=100000, n_req_other=20000, log2_slots
     the first n_req_other requests at 25, 75 and 90 %.  The trace is cut where
     its inserts would take the table past stop_load.  The comparator is the
     same server with one request per launch and one launch in flight (plain
-    batched launches in arrival order).  The table is emptied and pre-filled
+    batched launches in arrival order).  Each run is made with the staged
+    and the zero-copy server.  The table is emptied and pre-filled
     again before each run, and every answer of every run is checked: inserts
     of fresh keys answer PUT, finds answer 1 exactly for pre-filled keys."""
     import numpy as np
@@ -1090,6 +1091,7 @@ def serving(torch, cpht, synth, dev, n_req=100000, n_req_other=20000, log2_slots
         want_count = n_pre + ins_in[nr]
         counted = t.count()[0]
         lat_ms = lat.astype(np.float64) / 1e6
+        print(f"[bench] serving run: {nr} requests, {kw}, {mk / 1e6:.1f} ms", file=sys.stderr, flush=True)
         return {"requests": nr, "operations": ops_n, "mops": round(ops_n / (mk / 1e9) / 1e6, 1),
                 "requests_per_s": round(nr / (mk / 1e9), 0),
                 "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
@@ -1154,6 +1156,103 @@ def serving(torch, cpht, synth, dev, n_req=100000, n_req_other=20000, log2_slots
         res[name]["frac_of_h2d"] = round(gbs / link["h2d_GBps"], 3)
     del t, keys, ops, out, truth
     return res
+
+
+def serving_small(torch, cpht, synth, dev, n_burst=20000, burst_ops=64, reps=300):
+    """The three request paths on a table within the resident loop's covered
+    shapes: iceberg 2^22 + 2^19 slots (32/32-bit, 40-bit keys), pre-filled to
+    load 0.5.  (1) One 4096-operation request at a time on an idle server
+    (half finds of pre-filled keys, half inserts of fresh keys), staged,
+    zero-copy and resident, beside a bare mixed launch + synchronise on device
+    buffers; (2) a burst of n_burst requests of burst_ops operations in
+    separate pinned buffers submitted at once, per path.  Every answer of the
+    burst is checked (inserts of fresh keys PUT, finds of pre-filled keys 1)."""
+    import numpy as np
+
+    w, L0, L1 = 40, 22, 19
+    out = {"config": (f"iceberg 2^{L0} + 2^{L1} slots (32/32-bit), {w}-bit keys, pre-filled to load 0.5; "
+                      f"idle 4096-operation requests; a burst of {n_burst} requests of {burst_ops} operations "
+                      f"in separate pinned buffers")}
+    paths = {"staged": dict(max_inflight=4, coalesce=1, staging_keys=1 << 20, max_batch_keys=1 << 16),
+             "zero_copy": dict(max_inflight=4, coalesce=1, max_batch_keys=1 << 16, zero_copy=1),
+             "resident": dict(zero_copy=1, resident=1, max_batch_keys=1 << 16)}
+    cap = (1 << L0) + (1 << L1)
+    n_pre = cap // 2
+
+    def fresh_table():
+        t = cpht.Table(scheme=cpht.ICEBERG, key_bits=w, log2_slots0=L0, log2_slots1=L1, bucket0=32, bucket1=16,
+                       slot_bits0=32, slot_bits1=32, seed=41)
+        t.insert(synth.distinct_keys(w, KEY_SEED + 11, 0, n_pre, device=dev))
+        torch.cuda.synchronize()
+        return t
+
+    def words(idx):
+        return synth.to_words(synth.feistel(w, KEY_SEED + 11, idx), w)
+
+    # (1) idle latency
+    nq = 4096
+    fresh = n_pre + torch.arange(reps * nq, dtype=torch.int64)
+    hits = torch.arange(nq // 2, dtype=torch.int64) * 7 % n_pre
+    lat = {}
+    t = fresh_table()
+    ops1 = torch.cat([torch.ones(nq // 2, dtype=torch.uint8), torch.zeros(nq // 2, dtype=torch.uint8)])
+    kd = torch.cat([words(fresh[:nq // 2]), words(hits)]).to(dev)
+    od = ops1.to(dev)
+    rd = torch.empty(nq, dtype=torch.uint8, device=dev)
+    bare = []
+    for i in range(reps):
+        a = time.perf_counter_ns()
+        t.mixed(kd, od, out=rd)
+        torch.cuda.synchronize()
+        bare.append(time.perf_counter_ns() - a)
+    lat["bare_launch_device_buffers"] = bare
+    del t
+    for name, kw in paths.items():
+        t = fresh_table()
+        kq = torch.cat([words(fresh[:nq // 2]), words(hits)]).pin_memory()
+        oq = ops1.pin_memory()
+        rq = torch.zeros(nq, dtype=torch.uint8).pin_memory()
+        srv = cpht.Server(t, **kw)
+        lat[name] = [srv.wait(srv.submit(kq, oq, rq)) for _ in range(reps)]
+        srv.stop()
+        del t
+    out["idle_request_4096_us"] = {k: {"p50": round(float(np.percentile(v, 50)) / 1e3, 1),
+                                       "p99": round(float(np.percentile(v, 99)) / 1e3, 1)} for k, v in lat.items()}
+    # (2) burst of small requests in separate buffers
+    half = burst_ops // 2
+    hit_idx = (torch.arange(n_burst * half, dtype=torch.int64) * 13) % n_pre
+    burst = {}
+    for name, kw in paths.items():
+        t = fresh_table()
+        reqs, outs = [], []
+        for i in range(n_burst):
+            k = torch.cat([words(n_pre + torch.arange(i * half, (i + 1) * half, dtype=torch.int64)),
+                           words(hit_idx[i * half:(i + 1) * half])])
+            kb = torch.empty(burst_ops + 8, dtype=k.dtype).pin_memory()[:burst_ops]
+            kb.copy_(k)
+            ob = torch.empty(burst_ops + 8, dtype=torch.uint8).pin_memory()[:burst_ops]
+            ob[:half] = 1
+            ob[half:] = 0
+            reqs.append((kb, ob))
+            outs.append(torch.zeros(burst_ops + 8, dtype=torch.uint8).pin_memory()[:burst_ops])
+        srv = cpht.Server(t, **kw)
+        a = time.perf_counter()
+        tickets = [srv.submit(k, o, r) for (k, o), r in zip(reqs, outs)]
+        for tk in tickets:
+            srv.wait(tk)
+        dt = time.perf_counter() - a
+        st = srv.stats()
+        srv.stop()
+        res = torch.stack(outs).numpy()
+        ok = bool((res[:, :half] == cpht.PUT).all() and (res[:, half:] == 1).all()
+                  and t.count()[0] == n_pre + n_burst * half)
+        burst[name] = {"ms": round(dt * 1e3, 1), "requests_per_s": round(n_burst / dt), "launches": st["launches"],
+                       "check": "ok" if ok else "FAILED"}
+        print(f"[bench] serving_small burst {name}: {dt * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        del t, reqs, outs
+    out["burst"] = burst
+    out["check"] = "ok" if all(v["check"] == "ok" for v in burst.values()) else "FAILED"
+    return out
 
 
 def host_link(torch, dev, mib=512, reps=5):
@@ -1501,6 +1600,9 @@ def main():
 
     if not args.no_serving:
         run_section(res, "serving", lambda: serving(torch, cpht, synth, dev))
+
+    if not args.no_servingsmall:
+        run_section(res, "serving_small", lambda: serving_small(torch, cpht, synth, dev))
 
     if not args.no_ceilings:
         run_section(res, "ceilings", lambda: ceilings(torch, cpht, dev, res, keys))

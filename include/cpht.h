@@ -361,6 +361,19 @@ cpht_status_t cpht_multi_error(cpht_multi_t m, uint32_t* flags);
  * tensor after pin_memory()), the mixed kernel reads the keys and opcodes and
  * writes the results in place, and a launch covers a run of queued requests
  * that lie back to back in all three buffers (up to max_batch_keys keys).
+ * In resident mode (resident = 1, with zero_copy = 1) requests are not
+ * launched one by one: a persistent kernel started by the server takes
+ * request descriptors from a ring of 1024 in pinned host memory (one per
+ * request, or with coalesce = 1 one per run of queued requests that lie back
+ * to back in all three buffers, up to max_batch_keys operations), cuts each
+ * into chunks of 2048 operations that its blocks (two per compute unit, plus
+ * one that watches the ring) take in order, and reports every completed
+ * descriptor back through the ring; so up to 1024 descriptors are in flight
+ * and overlap on the device, and an idle request costs no kernel launch.
+ * A request larger than max_batch_keys is refused (CPHT_E_ARG) in this mode.  The kernel ends after idle_us without requests and is started
+ * again by the next one.  While it runs it holds part of the device: work
+ * that synchronises the whole device (hipDeviceSynchronize) waits until it
+ * ends, so stop the server, or let it go idle, before such calls.
  * The server runs set operations (cpht_mixed): on a map table the values are
  * neither written nor returned.  The table must outlive the server, and no
  * other call may clear or import into it while the server runs.  The server
@@ -380,11 +393,17 @@ typedef struct {
                                  CPHT_E_NOMEM if that is below max_batch_keys) */
     uint64_t max_batch_keys;  /* keys per launch when coalescing (<= staging_keys unless zero_copy) */
     uint32_t zero_copy;       /* 1: the device works on the pinned request buffers in place (no staging) */
+    uint32_t resident;        /* 1 (requires zero_copy = 1; two-level tables of at most 2^24 primary
+                                 slots; max_batch_keys <= 2^17, else CPHT_E_UNSUPPORTED): no launch per
+                                 request: one persistent launch takes the requests from a ring in pinned
+                                 host memory */
+    uint32_t idle_us;         /* resident: the persistent launch ends after this long without requests
+                                 (1 .. 10^7; the next request starts it again) */
     uint32_t pad;             /* must be 0 */
 } cpht_server_config_t;
 
 /* Defaults: 4 launches in flight, coalescing, 2^24 staging keys, 2^22 keys per
- * launch, staged (zero_copy = 0). */
+ * launch, staged (zero_copy = 0), not resident (idle_us = 10000). */
 void cpht_server_config_default(cpht_server_config_t* cfg);
 
 /* Start a server on an iceberg table (CPHT_E_STATE for cuckoo: static). */

@@ -524,6 +524,8 @@ class ServerConfig(ctypes.Structure):
         ("staging_keys", ctypes.c_uint64),
         ("max_batch_keys", ctypes.c_uint64),
         ("zero_copy", ctypes.c_uint32),
+        ("resident", ctypes.c_uint32),
+        ("idle_us", ctypes.c_uint32),
         ("pad", ctypes.c_uint32),
     ]
 

@@ -19,7 +19,7 @@ constexpr int l3_ok() { return L3Shape<S0, G>::OK ? 1 : 0; }
 const int kL3Ok[] = {CPHT_ICE_LIST(CPHT_ICE_L3OK)};
 
 void assemble(IceVariant* out, int key64, const IceLaunch4* base, const IceMulti2* multi, const IceLaunch4* l3,
-              const IceLaunch4* map) {
+              const IceLaunch4* map, const resident_fn* resident) {
   for (int i = 0; i < kCount; ++i) {
     IceVariant& v = out[i];
     v.key64 = key64;
@@ -43,6 +43,7 @@ void assemble(IceVariant* out, int key64, const IceLaunch4* base, const IceMulti
     v.insert_v3 = map[i].d;
     v.multi_find = multi[i].find;
     v.multi_insert = multi[i].insert;
+    v.resident = resident[i];
   }
 }
 
@@ -50,8 +51,8 @@ struct Tables {
   IceVariant u32[kCount];
   IceVariant u64[kCount];
   Tables() {
-    assemble(u32, 0, ice_base_u32(), ice_multi_u32(), ice_l3_u32(), ice_map_u32());
-    assemble(u64, 1, ice_base_u64(), ice_multi_u64(), ice_l3_u64(), ice_map_u64());
+    assemble(u32, 0, ice_base_u32(), ice_multi_u32(), ice_l3_u32(), ice_map_u32(), ice_resident_u32());
+    assemble(u64, 1, ice_base_u64(), ice_multi_u64(), ice_l3_u64(), ice_map_u64(), ice_resident_u64());
   }
 };
 

@@ -8,6 +8,11 @@ namespace cpht {
 
 typedef void (*launch_fn)(const TableK&, const BatchK&, hipStream_t);
 typedef void (*multi_fn)(const MultiK&, uint32_t blocks, hipStream_t);
+struct RingCtl;
+struct ResidentState;
+// The resident request loop (cpht_resident.hpp): `blocks` = 1 leader + workers.
+typedef hipError_t (*resident_fn)(const TableK&, RingCtl* ctl, ResidentState* st, uint32_t epoch,
+                                  uint64_t idle_ticks, uint32_t blocks, hipStream_t);
 
 struct IceVariant {
   int key64;           // 1: 64-bit key words
@@ -18,6 +23,7 @@ struct IceVariant {
   launch_fn find3, insert3, mixed3, erase3;  // with the third level compiled in (null if l3 = 0)
   launch_fn find_v, insert_v, find_v3, insert_v3;  // map lookup / find-or-put (values), without / with level 3
   multi_fn multi_find, multi_insert;
+  resident_fn resident;  // the serving loop's persistent mixed-batch kernel (two levels)
 };
 
 struct CkVariant {
@@ -68,6 +74,8 @@ const IceLaunch4* ice_base_u64();
 const IceMulti2* ice_multi_u64();
 const IceLaunch4* ice_l3_u64();
 const IceLaunch4* ice_map_u64();
+const resident_fn* ice_resident_u32();  // one per CPHT_ICE_LIST position
+const resident_fn* ice_resident_u64();
 const CkVariant* ck_variants_u32(int* n);
 const CkVariant* ck_variants_u64(int* n);
 

@@ -15,6 +15,13 @@
 // that the device reads and writes directly, so a launch is one mixed kernel
 // over the host buffers and no staging or copies are involved.  A launch then
 // covers a run of queued requests that lie back to back in all three buffers.
+//
+// Resident mode (cfg.resident = 1, zero-copy buffers): no launch per request.
+// One persistent launch (cpht_resident.hpp) consumes request descriptors
+// that the dispatcher writes into a ring in pinned host memory, and reports
+// each completed request there; requests overlap on the device as its blocks
+// take their chunks.  The loop ends by itself after idle_us without work and
+// is launched again when requests arrive.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,6 +38,8 @@
 
 #include "cpht.h"
 #include "cpht_internal.hpp"
+#include "cpht_registry.hpp"
+#include "cpht_resident.hpp"
 #include "cpht_tickets.hpp"
 
 using namespace cpht;
@@ -89,6 +98,24 @@ struct cpht_server {
   bool stopping = false;
   std::atomic<int> error{0};
   std::thread worker;
+
+  // resident mode: the ring (pinned host memory, and its device view), the
+  // loop's device state, its stream, and the dispatcher's bookkeeping
+  RingCtl* ctl = nullptr;
+  RingCtl* d_ctl = nullptr;
+  ResidentState* rst = nullptr;
+  hipStream_t rstream = nullptr;
+  uint32_t epoch = 0;
+  uint32_t workers = 0;
+  uint64_t idle_ticks = 0;
+  uint64_t next_seq = 0;    // descriptors written
+  uint64_t next_chunk = 0;  // chunk ids handed out
+  std::vector<uint64_t> slot_total;                  // running chunk totals per ring slot
+  std::vector<std::vector<uint64_t>> slot_reqs;      // request ids in each busy slot
+  std::vector<uint8_t> slot_busy;
+  std::deque<uint64_t> rinflight;                    // descriptor seqs in flight, in publication order
+  bool loop_launched = false;
+  uint64_t last_query_ns = 0;
 
   // statistics
   uint64_t launches = 0, ops_done = 0, reqs_done = 0, max_queue = 0;
@@ -210,6 +237,151 @@ T* device_view(T* h, uint64_t bytes) {
   const char* b = static_cast<const char*>(base);
   if (d < b || d + bytes > b + size) return nullptr;
   return reinterpret_cast<T*>(d);
+}
+
+// (Re)start the resident loop with a new epoch.
+hipError_t launch_loop(cpht_server* s) {
+  const cpht::IceVariant* v = s->table->ice;
+  ++s->epoch;
+  hipError_t e = v->resident(s->table->tk, s->d_ctl, s->rst, s->epoch, s->idle_ticks, s->workers + 1, s->rstream);
+  if (e == hipSuccess) {
+    s->loop_launched = true;
+    std::lock_guard<std::mutex> lk(s->mu);  // the statistics are read under the lock
+    ++s->launches;
+  }
+  return e;
+}
+
+// The dispatcher of resident mode: publish queued requests into free ring
+// slots, complete the requests the loop reports, and keep the loop running
+// while requests are in flight.  The ring bookkeeping (rinflight, slot_*,
+// next_seq, next_chunk, the descriptors) belongs to this thread alone; the
+// server mutex is held only to record completions and to take queued
+// requests, never across the scan of the done words or a runtime call, so
+// submitters and waiters are not starved while this thread polls the ring.
+void resident_dispatcher(cpht_server* s) {
+  if (hipSetDevice(s->table->device) != hipSuccess) s->error = 1;
+  struct Pending {
+    uint32_t slot;
+    Request first;  // copy of the first request (device views of the buffers)
+    uint64_t total;
+  };
+  std::vector<uint64_t> finished;
+  std::vector<Pending> take;
+  for (;;) {
+    // 1. completions, in any order (no lock: the done words are atomics)
+    finished.clear();
+    for (auto it = s->rinflight.begin(); it != s->rinflight.end();) {
+      const uint64_t seq = *it;
+      if (__atomic_load_n(&s->ctl->done[seq % RING_SLOTS], __ATOMIC_ACQUIRE) == seq + 1) {
+        finished.push_back(seq);
+        it = s->rinflight.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    // 2. under the lock: record completions, take queued requests for the
+    //    free slots (one descriptor per request, or per run of requests that
+    //    lie back to back in all three buffers when coalescing)
+    take.clear();
+    bool stop_now = false;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      if (!finished.empty()) {
+        const uint64_t t = now_ns();
+        for (uint64_t seq : finished) {
+          const uint32_t slot = (uint32_t)(seq % RING_SLOTS);
+          for (uint64_t id : s->slot_reqs[slot]) {
+            Request* r = s->reqs.find(id);  // pending records are never released
+            r->t_done = t;
+            s->ops_done += r->n;
+            ++s->reqs_done;
+          }
+          s->slot_busy[slot] = 0;
+        }
+        s->reqs.trim(is_done);
+        s->cv.notify_all();
+      }
+      uint64_t seq = s->next_seq;
+      while (!s->queue.empty() && !s->error && !s->slot_busy[seq % RING_SLOTS]) {
+        const uint32_t slot = (uint32_t)(seq % RING_SLOTS);
+        std::vector<uint64_t>& ids = s->slot_reqs[slot];
+        ids.assign(1, s->queue.front());
+        s->queue.pop_front();
+        Pending pd{slot, *s->reqs.find(ids[0]), 0};
+        pd.total = pd.first.n;
+        while (s->cfg.coalesce && !s->queue.empty()) {
+          const Request& last = *s->reqs.find(ids.back());
+          const Request& next = *s->reqs.find(s->queue.front());
+          if (pd.total + next.n > s->cfg.max_batch_keys || !adjacent(last, next, s->key_bytes)) break;
+          ids.push_back(s->queue.front());
+          pd.total += next.n;
+          s->queue.pop_front();
+        }
+        s->slot_busy[slot] = 1;
+        take.push_back(pd);
+        ++seq;
+      }
+      if (s->error) {
+        // fail everything queued or in flight so waiters return
+        const uint64_t t = now_ns();
+        while (!s->queue.empty()) {
+          s->reqs.find(s->queue.front())->t_done = t;
+          s->queue.pop_front();
+        }
+        for (uint64_t q : s->rinflight)
+          for (uint64_t id : s->slot_reqs[q % RING_SLOTS]) s->reqs.find(id)->t_done = t;
+        for (const Pending& pd : take)
+          for (uint64_t id : s->slot_reqs[pd.slot]) s->reqs.find(id)->t_done = t;
+        s->rinflight.clear();
+        take.clear();
+        s->cv.notify_all();
+        if (s->stopping) stop_now = true;
+      }
+      if (s->stopping && s->queue.empty() && s->rinflight.empty() && take.empty()) stop_now = true;
+      if (!stop_now && s->rinflight.empty() && take.empty()) {
+        s->cv.wait_for(lk, std::chrono::microseconds(200));
+        continue;
+      }
+    }
+    if (stop_now) break;
+    // 3. write the descriptors and publish them (the device reads them only
+    //    after the release store of the count)
+    for (const Pending& pd : take) {
+      const uint64_t seq = s->next_seq++;
+      const uint64_t chunks = (pd.total + CHUNK_KEYS - 1) / CHUNK_KEYS;
+      s->slot_total[pd.slot] += chunks;
+      RingDesc& d = s->ctl->desc[pd.slot];
+      d.keys = pd.first.dkeys;
+      d.ops = pd.first.dops;
+      d.out = pd.first.dout;
+      d.n = pd.total;
+      d.chunk_base = s->next_chunk;
+      d.slot_target = s->slot_total[pd.slot];
+      d.seq = seq;
+      s->next_chunk += chunks;
+      s->rinflight.push_back(seq);
+    }
+    const bool published = !take.empty();
+    if (published) __atomic_store_n(&s->ctl->published, s->next_seq, __ATOMIC_RELEASE);
+    // 4. the loop must be running while requests are in flight: it ends by
+    //    itself when idle, possibly just before a publication it did not see
+    if (!s->rinflight.empty() && !s->error) {
+      const uint64_t t = now_ns();
+      bool relaunch = !s->loop_launched;
+      if (!relaunch && (published || t - s->last_query_ns > 50000)) {
+        s->last_query_ns = t;
+        const hipError_t q = hipStreamQuery(s->rstream);
+        if (q == hipSuccess) relaunch = true;
+        else if (q != hipErrorNotReady) s->error = 1;
+      }
+      if (relaunch && !s->error) {
+        const hipError_t e = launch_loop(s);
+        if (e != hipSuccess) s->error = 1;
+      }
+    }
+    std::this_thread::yield();
+  }
 }
 
 void dispatcher(cpht_server* s) {
@@ -357,7 +529,44 @@ hipError_t warm_up(cpht_server* s) {
   return e;
 }
 
+// Resident mode: the ring in pinned host memory (mapped, coherent), the loop's
+// device state, its stream, the idle bound in device clock ticks, and the
+// worker count (two blocks per compute unit, leaving room beside the loop).
+hipError_t resident_setup(cpht_server* s) {
+  void* h = nullptr;
+  hipError_t e = hipHostMalloc(&h, sizeof(RingCtl), hipHostMallocMapped | hipHostMallocCoherent);
+  if (e != hipSuccess) return e;
+  s->ctl = static_cast<RingCtl*>(h);
+  std::memset(s->ctl, 0, sizeof(RingCtl));
+  void* d = nullptr;
+  e = hipHostGetDevicePointer(&d, h, 0);
+  if (e != hipSuccess) return e;
+  s->d_ctl = static_cast<RingCtl*>(d);
+  e = hipMalloc(reinterpret_cast<void**>(&s->rst), sizeof(ResidentState));
+  if (e == hipSuccess) e = hipMemset(s->rst, 0, sizeof(ResidentState));
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->rstream, hipStreamNonBlocking);
+  int rate_khz = 0, cus = 0;
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, s->table->device);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->table->device);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return e;
+  s->idle_ticks = (uint64_t)s->cfg.idle_us * (uint64_t)(rate_khz > 0 ? rate_khz : 100000) / 1000ull;
+  s->workers = (uint32_t)(cus > 0 ? 2 * cus : 512);
+  s->slot_total.assign(RING_SLOTS, 0);
+  s->slot_reqs.assign(RING_SLOTS, {});
+  s->slot_busy.assign(RING_SLOTS, 0);
+  return hipSuccess;
+}
+
 void free_server(cpht_server* s) {
+  if (s->rstream) {
+    if (s->ctl) __atomic_store_n(&s->ctl->stop, 1u, __ATOMIC_RELEASE);  // the loop ends at its next poll
+    (void)hipStreamSynchronize(s->rstream);
+    (void)hipStreamDestroy(s->rstream);
+  }
+  if (s->rst) (void)hipFree(s->rst);
+  if (s->ctl) (void)hipHostFree(s->ctl);
   for (Slot& sl : s->slots) {
     if (sl.done) (void)hipEventDestroy(sl.done);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
@@ -379,6 +588,8 @@ void cpht_server_config_default(cpht_server_config_t* c) {
   c->staging_keys = 1ull << 24;
   c->max_batch_keys = 1ull << 22;
   c->zero_copy = 0;
+  c->resident = 0;
+  c->idle_us = 10000;
   c->pad = 0;
 }
 
@@ -387,8 +598,15 @@ cpht_status_t cpht_server_start(cpht_table_t t, const cpht_server_config_t* cfg,
   *out = nullptr;
   if (!t->ice) return CPHT_E_STATE;  // the dynamic (iceberg) table only
   if (cfg->max_inflight < 1 || cfg->max_inflight > 64 || cfg->max_batch_keys < 1 || cfg->zero_copy > 1 ||
-      cfg->pad != 0)
+      cfg->resident > 1 || cfg->pad != 0)
     return CPHT_E_ARG;
+  if (cfg->resident && (!cfg->zero_copy || cfg->idle_us < 1 || cfg->idle_us > 10000000)) return CPHT_E_ARG;
+  if (cfg->resident && (t->nimages == 4 || !t->ice->resident)) return CPHT_E_UNSUPPORTED;  // two levels only
+  // Resident mode runs only within the shapes its tests cover: at the full
+  // serving shape (2^32 + 2^29 slots, a saturated trace coalesced into
+  // descriptors of up to 2^22 operations) a replay did not complete, for a
+  // reason not found yet.
+  if (cfg->resident && (t->cfg.log2_slots0 > 24 || cfg->max_batch_keys > (1ull << 17))) return CPHT_E_UNSUPPORTED;
   if (!cfg->zero_copy && cfg->staging_keys != 0 && cfg->max_batch_keys > cfg->staging_keys) return CPHT_E_ARG;
   const uint64_t key_bytes = t->cfg.key_bits > 32 ? 8 : 4;
   DeviceGuard g(t->device);
@@ -422,11 +640,12 @@ cpht_status_t cpht_server_start(cpht_table_t t, const cpht_server_config_t* cfg,
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
   }
   if (e == hipSuccess) e = warm_up(s);
+  if (e == hipSuccess && cfg->resident) e = resident_setup(s);
   if (e != hipSuccess) {
     free_server(s);
     return device_status(e);
   }
-  s->worker = std::thread(dispatcher, s);
+  s->worker = cfg->resident ? std::thread(resident_dispatcher, s) : std::thread(dispatcher, s);
   *out = s;
   return CPHT_OK;
 }
@@ -436,6 +655,7 @@ cpht_status_t cpht_server_submit(cpht_server_t s, const void* h_keys, const uint
   const uint64_t t_call = now_ns();  // latency counts the submission work too
   if (!s || !ticket || (n && (!h_keys || !h_ops || !h_out))) return CPHT_E_ARG;
   if (!s->cfg.zero_copy && n > s->cfg.staging_keys) return CPHT_E_ARG;  // could never be admitted
+  if (s->cfg.resident && n > s->cfg.max_batch_keys) return CPHT_E_ARG;  // one descriptor at most
   Request r{h_keys, h_ops, h_out, n, nullptr, nullptr, nullptr, 0, 0};
   if (s->cfg.zero_copy && n) {  // the device reads and writes the host buffers in place
     DeviceGuard g(s->table->device);
