@@ -23,8 +23,9 @@
  *      secondary index for iceberg, Sec. 3 Alg. 1) and the remainder
  *      (Sec. 2.4), or the full permuted key for a non-compact table.  A
  *      deleted key leaves a tombstone, the word 1 (occupancy bit clear): a
- *      slot that is not EMPTY but holds no key, so non-empty slots stay
- *      consecutive (Sec. 2.2 "Lookup", Sec. 3 "Limitations").
+ *      slot that is not EMPTY but holds no key, so the non-empty slots of an
+ *      iceberg bucket stay consecutive (Sec. 2.2 "Lookup", Sec. 3
+ *      "Limitations").
  *   4. Iceberg find-or-put, run sequentially as the simplified find-or-put of
  *      Appendix A (Alg. 5) over the slot order of Definition 1.
  *   5. Iceberg lookup (Sec. 2.3 "Lookup", levels 1 and 2).
@@ -38,6 +39,12 @@
  *      property of Appendix A Definition 2, no duplicates (Lemma 1), prefix
  *      filling of iceberg buckets, and the cuckoo early-exit invariant of
  *      Sec. 2.2 / 4.4).
+ *
+ * Parity unpinned: the load at which the first FULL answer appears (and the
+ * fill reached after it) depends on the permutations, the chain bound C and
+ * the victim rule; the paper gives only soft bounds (cuckoo with 16 or 32
+ * slots per bucket reaches 0.95, iceberg with 32 primary slots 0.9), which
+ * the tests check, and the GPU's value is reported beside this model's.
  *
  * Raw table image layout (shared contract with the GPU library, documented in
  * the public header): level x is an array of 2^nb_x buckets of B_x slots of
