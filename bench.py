@@ -53,7 +53,7 @@ SECTOR = 64  # write-back unit of a modified slot (measured: 67.0 B written per 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by the
 # copy-kernel calibration factors 2.0 / 1.0), profiles/cuckoo_c2_hbm_bytes.md.
 # Valid only for the kernel sources they were taken with (hash of KERNEL_SOURCES below).
-TRAFFIC = {"csrc_sha": "9bd1d34100d51734", "cuckoo_put": 25333017600, "cuckoo_find": 11035480064}
+TRAFFIC = {"csrc_sha": "d690d9abc3ada6cc", "cuckoo_put": 25332912320, "cuckoo_find": 11035491456}
 
 
 # The sources the profiled cuckoo kernels are compiled from.
@@ -62,7 +62,7 @@ KERNEL_SOURCES = ("cpht_device.hpp", "cpht_cuckoo.hpp", "cpht_registry.hpp", "in
 # Measured HBM bytes per operation (read + written, same calibration) of the
 # iceberg kernels at the iceberg_static shape, profiles/iceberg_hbm_bytes.md;
 # valid for the iceberg sources they were taken with.
-ICE_TRAFFIC = {"src_sha": "7af84e15309d9e7a", "insert_16_32": 222.6, "find_16_32": 214.3,
+ICE_TRAFFIC = {"src_sha": "c19e6ef2876f332e", "insert_16_32": 222.6, "find_16_32": 214.3,
                "insert_64_64": 350.9, "find_64_64": 344.0}
 ICE_SOURCES = ("cpht_device.hpp", "cpht_iceberg.hpp", "cpht_registry.hpp", "inst_iceberg_u64.hip")
 
