@@ -51,7 +51,7 @@ struct RingDesc {
 struct RingCtl {
   uint64_t published;  // descriptors published by the host (descriptor seq sits at slot seq % RING_SLOTS)
   uint32_t stop;       // host: 1 = end the loop
-  uint32_t pad;
+  uint32_t fault;      // device: 1 = a block found no request for its chunk (the ring protocol was broken)
   uint64_t done[RING_SLOTS];  // device: seq + 1 once request seq has completed
   RingDesc desc[RING_SLOTS];
 };
@@ -184,7 +184,10 @@ __global__ __launch_bounds__(256) void iceberg_resident_kernel(TableK T, RingCtl
         if (seq < m) {
           s_desc = dd[seq % RING_SLOTS];
         } else {
-          cmd = 0;  // not found: cannot happen while the host keeps the ring protocol; end this block
+          // cannot happen while the host keeps the ring protocol: report it
+          // (the host then fails every request instead of waiting) and end this block
+          __hip_atomic_store(&ctl->fault, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+          cmd = 0;
         }
       }
       s_cmd = cmd;

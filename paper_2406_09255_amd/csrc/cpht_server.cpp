@@ -270,6 +270,7 @@ void resident_dispatcher(cpht_server* s) {
   std::vector<Pending> take;
   for (;;) {
     // 1. completions, in any order (no lock: the done words are atomics)
+    if (__atomic_load_n(&s->ctl->fault, __ATOMIC_ACQUIRE) != 0u) s->error = 1;
     finished.clear();
     for (auto it = s->rinflight.begin(); it != s->rinflight.end();) {
       const uint64_t seq = *it;
