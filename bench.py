@@ -1288,7 +1288,9 @@ def ceilings(torch, cpht, dev, res, split_keys):
         buf = torch.zeros(nbytes // 4, dtype=torch.int32, device=dev)
         row = {}
         for kind, name in ((cpht.PROBE_LINES, "line_reads"), (cpht.PROBE_CAS, "cas"),
-                           (cpht.PROBE_CAS64, "cas64"), (cpht.PROBE_LINE_CAS, "line_read_then_cas")):
+                           (cpht.PROBE_CAS64, "cas64"), (cpht.PROBE_LINE_CAS, "line_read_then_cas"),
+                           (cpht.PROBE_HALF_LINES, "half_line_reads"),
+                           (cpht.PROBE_LINES_NT, "line_reads_nontemporal")):
             ops = 1 << 27
             cpht.probe(kind, buf, ops, 1, sink)  # warm-up (and first touch)
             times = []
@@ -1302,6 +1304,7 @@ def ceilings(torch, cpht, dev, res, split_keys):
             ms = sorted(times)[1]
             row[name] = {"G_per_s": round(done / (ms / 1000.0) / 1e9, 2), "ms": round(ms, 3)}
         row["line_reads"]["GB_per_s"] = round(row["line_reads"]["G_per_s"] * 128, 1)
+        row["half_line_reads"]["GB_per_s"] = round(row["half_line_reads"]["G_per_s"] * 64, 1)
         out[label] = row
         del buf
     # the benchmark's kernels against these ceilings (lines per op from the oracle model)

@@ -453,7 +453,9 @@ cpht_status_t cpht_server_replay(cpht_server_t s, uint64_t n_requests, const uin
  *           read in order (wrapping round), each split under three
  *           permutations of 37-bit keys into a 22-bit address and a stored
  *           form, as the benchmark table does; nothing is written but d_sink
- *           (practically never).  One operation = one key's three splits.
+ *           (practically never).  One operation = one key's three splits;
+ *   kind 5: random 64-byte reads (half lines), 4 lanes x 16 bytes;
+ *   kind 6: random 128-byte line reads as kind 0, with non-temporal loads.
  * `ops` is rounded up to a multiple of 16384; *ops_done receives the count
  * actually issued.  Asynchronous on `stream`. */
 cpht_status_t cpht_probe(uint32_t kind, void* d_buf, uint64_t bytes, uint64_t ops, uint64_t seed, uint32_t* d_sink,

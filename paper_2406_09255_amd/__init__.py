@@ -171,7 +171,7 @@ def variants(scheme: int) -> list[dict]:
     return out
 
 
-PROBE_LINES, PROBE_CAS, PROBE_LINE_CAS, PROBE_CAS64, PROBE_SPLIT = 0, 1, 2, 3, 4
+PROBE_LINES, PROBE_CAS, PROBE_LINE_CAS, PROBE_CAS64, PROBE_SPLIT, PROBE_HALF_LINES, PROBE_LINES_NT = range(7)
 
 
 def probe(kind: int, buf: torch.Tensor, ops: int, seed: int, sink: torch.Tensor, stream=None) -> int:

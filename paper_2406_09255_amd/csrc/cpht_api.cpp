@@ -627,7 +627,7 @@ int cpht_variant_info(uint32_t scheme, int i, uint32_t* info) {
 
 cpht_status_t cpht_probe(uint32_t kind, void* d_buf, uint64_t bytes, uint64_t ops, uint64_t seed, uint32_t* d_sink,
                          uint64_t* ops_done, void* stream) {
-  if (kind > 4 || !d_buf || !d_sink || bytes < 4096 || !pow2(bytes) || ops == 0) return CPHT_E_ARG;
+  if (kind > 6 || !d_buf || !d_sink || bytes < 4096 || !pow2(bytes) || ops == 0) return CPHT_E_ARG;
   // whole 256-thread blocks: 16384 operations per block for every kind
   const uint64_t unit = 16384;
   const uint64_t n = (ops + unit - 1) / unit * unit;

@@ -37,6 +37,32 @@ __global__ __launch_bounds__(256) void probe_lines_kernel(const uint4* buf, uint
   if (acc == 0x9E3779B9u) sink[0] = acc;  // keeps the loads live; practically never stores
 }
 
+// Each group of LANES lanes reads `per` random units of LANES x 16 bytes
+// (4 lanes: 64-byte half lines, 8 lanes: whole lines), with plain or with
+// non-temporal loads.
+template <int LANES, bool NT>
+__global__ __launch_bounds__(256) void probe_units_kernel(const uint4* buf, uint64_t unit_mask, uint32_t per,
+                                                          uint64_t seed, uint32_t* sink) {
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t group = gid / LANES;
+  const uint32_t r = (uint32_t)(gid % LANES);
+  uint32_t acc = 0;
+#pragma unroll 1
+  for (uint32_t i = 0; i < per; i += INFLIGHT) {
+    u32x4 v[INFLIGHT];
+#pragma unroll
+    for (int d = 0; d < INFLIGHT; ++d) {
+      const u32x4* p = reinterpret_cast<const u32x4*>(buf + line_of(group, i + d, seed, unit_mask) * LANES + r);
+      if constexpr (NT) v[d] = __builtin_nontemporal_load(p);
+      else v[d] = *p;
+    }
+#pragma unroll
+    for (int d = 0; d < INFLIGHT; ++d) acc ^= v[d].x ^ v[d].y ^ v[d].z ^ v[d].w;
+  }
+  if (acc == 0x9E3779B9u) sink[0] = acc;
+}
+
 // Each lane performs `per` CAS (expected 0) on random 32-bit words.
 __global__ __launch_bounds__(256) void probe_cas_kernel(uint32_t* buf, uint64_t word_mask, uint32_t per,
                                                         uint64_t seed, uint32_t* sink) {
@@ -177,6 +203,17 @@ hipError_t launch_probe(int kind, void* buf, uint64_t bytes, uint64_t ops, uint6
     const uint64_t threads = ops / per;
     hipLaunchKernelGGL(probe_cas64_kernel, dim3(grid_for(threads)), dim3(256), 0, s, static_cast<uint64_t*>(buf),
                        words - 1, per, seed, sink);
+  } else if (kind == 5 || kind == 6) {
+    // kind 5: random 64-byte half-line reads (4 lanes); kind 6: random lines, non-temporal loads
+    const uint64_t lanes = kind == 5 ? 4 : 8;
+    const uint64_t units = bytes / (16 * lanes);
+    const uint64_t threads = (ops / per) * lanes;
+    if (kind == 5)
+      hipLaunchKernelGGL((probe_units_kernel<4, false>), dim3(grid_for(threads)), dim3(256), 0, s,
+                         static_cast<const uint4*>(buf), units - 1, per, seed, sink);
+    else
+      hipLaunchKernelGGL((probe_units_kernel<8, true>), dim3(grid_for(threads)), dim3(256), 0, s,
+                         static_cast<const uint4*>(buf), units - 1, per, seed, sink);
   } else {
     // the headline table's shape: 37-bit keys, 2^22 buckets
     const uint32_t w = 37, nb = 22;

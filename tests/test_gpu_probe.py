@@ -52,14 +52,25 @@ def test_probe_cas64_and_split(gpu):
     assert torch.equal(keys, before)
 
 
+def test_probe_half_line_and_nontemporal_reads_leave_the_buffer(gpu):
+    buf = torch.arange(1 << 20, dtype=torch.int32, device=gpu)  # 4 MiB
+    sink = torch.zeros(1, dtype=torch.int32, device=gpu)
+    before = buf.clone()
+    for kind in (cpht.PROBE_HALF_LINES, cpht.PROBE_LINES_NT):
+        done = cpht.probe(kind, buf, 1 << 16, 13, sink)
+        torch.cuda.synchronize()
+        assert done == 1 << 16
+    assert torch.equal(buf, before)
+
+
 def test_probe_rejects_bad_buffers(gpu):
     sink = torch.zeros(1, dtype=torch.int32, device=gpu)
     with pytest.raises(cpht.CphtError):  # not a power of two
         cpht.probe(cpht.PROBE_LINES, torch.zeros(3000, dtype=torch.int32, device=gpu), 1024, 1, sink)
     with pytest.raises(cpht.CphtError):  # no operations
         cpht.probe(cpht.PROBE_LINES, torch.zeros(4096, dtype=torch.int32, device=gpu), 0, 1, sink)
-    with pytest.raises(cpht.CphtError):  # unknown kind
-        cpht.probe(5, torch.zeros(4096, dtype=torch.int32, device=gpu), 1024, 1, sink)
+    with pytest.raises(cpht.CphtError):  # no such probe
+        cpht.probe(7, torch.zeros(4096, dtype=torch.int32, device=gpu), 1024, 1, sink)
 
 
 def test_level_ptr_reads_back_the_image(gpu):
