@@ -141,6 +141,9 @@ SECTIONS = ("plain", "equal", "cachefree", "window", "sweep", "servingsmall", "s
 # Sections run only when named in --only (minutes of host time).
 OPT_IN = ("cpu_full",)
 
+# Fill factors of the paper's Put / Find benchmarks (Sec. 5.1).
+SWEEP_LOADS = (0.5, 0.6, 0.7, 0.75, 0.8, 0.85, 0.9, 0.95)
+
 # (slot bits, compact, slots per bucket) of the load sweep: compact 32-bit and
 # plain 64-bit slots at 8, 16 and 32 slots per bucket.
 SWEEP_SHAPES = ((32, 1, 32), (64, 0, 32), (32, 1, 16), (64, 0, 16), (32, 1, 8), (64, 0, 8))
@@ -694,6 +697,56 @@ def iceberg_static(torch, cpht, synth, dev, reps=3):
     rows["config"] = (f"iceberg 2^{L0} + 2^{L1} slots, B0=32, B1=16, {w}-bit keys; insert {n} distinct keys "
                       f"(load {LOAD}) in one batch, then 2^26 finds 50% hit")
     return rows
+
+
+def iceberg_sweep(torch, cpht, synth, dev, reps=2):
+    """The paper's iceberg Put / Find benchmarks (Sec. 5.1): 2^27 + 2^24 slots,
+    37-bit keys, 8, 16 and 32 slots per primary bucket (secondary buckets
+    half as large) with 16/32-bit (extra compact), 32/32-bit (compact) and
+    64/64-bit (plain) slots; for each fill factor of the sweep the table is
+    filled from empty with distinct keys in one batch and then queried with
+    2^26 distinct keys, half of them stored.  Rates are medians over `reps`
+    repetitions with a new permutation seed each; fill factors at which an
+    insert answered FULL are marked (iceberg reaches 0.9 only with 32-slot
+    primary buckets, Sec. 5.2)."""
+    w, L0, L1 = 37, 27, 24
+    cap = (1 << L0) + (1 << L1)
+    loads = tuple(x for x in SWEEP_LOADS if x <= 0.9)
+    n_max = int(max(loads) * cap)
+    keys = synth.distinct_keys(w, KEY_SEED + 21, 0, n_max, device=dev)
+    qs = {L: synth.find_queries(w, KEY_SEED + 21, int(L * cap), N_FIND, 0.5, Q_SEED + 21, device=dev)
+          for L in loads}
+    out = torch.empty(n_max, dtype=torch.uint8, device=dev)
+    found = torch.empty(N_FIND, dtype=torch.uint8, device=dev)
+    rows = []
+    for s0, s1 in ((16, 32), (32, 32), (64, 64)):
+        for b0 in (8, 16, 32):
+            t = cpht.Table(scheme=cpht.ICEBERG, key_bits=w, log2_slots0=L0, log2_slots1=L1, bucket0=b0,
+                           bucket1=b0 // 2, slot_bits0=s0, slot_bits1=s1, compact=int(s0 < 64), seed=5)
+            for L in loads:
+                n = int(L * cap)
+                ins, fnd = [], []
+                for rep in range(reps + 1):
+                    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+                    t.clear(900 + rep)
+                    e[0].record()
+                    t.insert(keys[:n], out[:n])
+                    e[1].record()
+                    t.find(qs[L], found)
+                    e[2].record()
+                    e[2].synchronize()
+                    if rep:
+                        ins.append(e[0].elapsed_time(e[1]))
+                        fnd.append(e[1].elapsed_time(e[2]))
+                full = int((out[:n] == cpht.FULL).sum().item())
+                rows.append({"slot_bits": f"{s0}/{s1}", "bucket0": b0, "load": L, "subtile": t.config.subtile,
+                             "insert_mops": round(n / (sorted(ins)[len(ins) // 2] / 1000.0) / 1e6, 1),
+                             "find_mops": round(N_FIND / (sorted(fnd)[len(fnd) // 2] / 1000.0) / 1e6, 1),
+                             "full": full})
+            del t
+    del keys, qs
+    return {"config": (f"iceberg 2^{L0} + 2^{L1} slots, {w}-bit keys, B1 = B0/2; fill from empty to each load in "
+                       f"one batch, then 2^26 finds 50% hit"), "rows": rows}
 
 
 def mixed_stream_check(torch, idx, ops, out, n_fresh, counted):
@@ -1550,7 +1603,7 @@ def main():
         run_section(res, "marginal_window", lambda: marginal_window(torch, cpht, keys, n_ins))
 
     if not args.no_sweep:
-        loads = (0.5, 0.7, 0.8, 0.9, 0.95)
+        loads = SWEEP_LOADS
         qs = {load: synth.find_queries(W_KEY, KEY_SEED, int(load * (1 << LOG2_SLOTS)), N_FIND, 0.5, Q_SEED + 7,
                                        device=dev) for load in loads}
         sweep = []
@@ -1583,6 +1636,7 @@ def main():
 
     if not args.no_iceberg:
         run_section(res, "iceberg_static", lambda: iceberg_static(torch, cpht, synth, dev))
+        run_section(res, "iceberg_sweep", lambda: iceberg_sweep(torch, cpht, synth, dev))
         run_section(res, "iceberg_mixed", lambda: iceberg_mixed(torch, cpht, synth, dev))
         run_section(res, "iceberg_zipf", lambda: iceberg_zipf(torch, cpht, synth, dev))
 
