@@ -256,7 +256,18 @@ def find_or_put(torch, cpht, synth, dev, reps=3):
         ("iceberg_16_32", dict(scheme=cpht.ICEBERG, key_bits=w, log2_slots0=L, log2_slots1=L - 3, bucket0=32,
                                bucket1=16, slot_bits0=16, slot_bits1=32, seed=5), ((0.0, 0.5), (0.5, 0.9), (0.8, 0.9))),
         ("iceberg_64_64", dict(scheme=cpht.ICEBERG, key_bits=w, log2_slots0=L, log2_slots1=L - 3, bucket0=32,
-                               bucket1=16, slot_bits0=64, slot_bits1=64, compact=0, seed=5), ((0.5, 0.9),)),
+                               bucket1=16, slot_bits0=64, slot_bits1=64, compact=0, seed=5),
+         ((0.0, 0.5), (0.5, 0.9))),
+    ]
+    # the smaller primary buckets of the paper's benchmark (they answer FULL
+    # before load 0.9, so their batches end at 0.5 and 0.6)
+    for b0 in (8, 16):
+        for s0, s1 in ((16, 32), (64, 64)):
+            shapes.append((f"iceberg_{s0}_{s1}_b{b0}",
+                           dict(scheme=cpht.ICEBERG, key_bits=w, log2_slots0=L, log2_slots1=L - 3, bucket0=b0,
+                                bucket1=b0 // 2, slot_bits0=s0, slot_bits1=s1, compact=int(s0 < 64), seed=5),
+                           ((0.0, 0.5), (0.4, 0.6))))
+    shapes += [
         ("cuckoo_32", dict(scheme=cpht.CUCKOO, key_bits=w, log2_slots0=L, bucket0=32, slot_bits0=32, seed=5),
          ((0.0, 0.5), (0.5, 0.9), (0.8, 0.9))),
         ("cuckoo_64", dict(scheme=cpht.CUCKOO, key_bits=w, log2_slots0=L, bucket0=32, slot_bits0=64, compact=0,
@@ -303,6 +314,12 @@ def find_or_put(torch, cpht, synth, dev, reps=3):
     m = {r["before"]: r["mops"] for r in res["iceberg_16_32"]}
     c = {r["before"]: r["mops"] for r in res["cuckoo_32"]}
     res["iceberg_vs_sorted_cuckoo"] = {str(k): round(m[k] / c[k], 2) for k in m if k in c}
+    # 16/32-bit against 64/64-bit iceberg per primary bucket size, batch 0 -> 0.5
+    def at(name, before):
+        return next(r["mops"] for r in res[name] if r["before"] == before)
+    res["iceberg_16_32_vs_64_64_load_0_to_0.5"] = {
+        str(b0): round(at(f"iceberg_16_32{sfx}", 0.0) / at(f"iceberg_64_64{sfx}", 0.0), 3)
+        for b0, sfx in ((8, "_b8"), (16, "_b16"), (32, ""))}
     return res
 
 
