@@ -1171,14 +1171,17 @@ def serving(torch, cpht, synth, dev, n_req=100000, n_req_other=20000, log2_slots
                 "check": "ok" if (wrong == 0 and counted == want_count) else
                          f"FAILED: {wrong} wrong answers, count {counted} (want {want_count})"}
 
-    cont = dict(max_inflight=4, coalesce=1, staging_keys=1 << 25, max_batch_keys=1 << 22)
-    plain = dict(max_inflight=1, coalesce=0, staging_keys=1 << 25, max_batch_keys=1 << 22)
+    # staging_keys = 0: the staged servers size their staging ring, the
+    # admission budget, from the device memory free when they start
+    cont = dict(max_inflight=4, coalesce=1, staging_keys=0, max_batch_keys=1 << 22)
+    plain = dict(max_inflight=1, coalesce=0, staging_keys=0, max_batch_keys=1 << 22)
     direct = dict(max_inflight=4, coalesce=1, max_batch_keys=1 << 22, zero_copy=1)
     res = {"config": (f"iceberg 2^{L0} + 2^{L1} slots (16/32-bit, {t.level_bytes(0) + t.level_bytes(1)} bytes), "
                       f"{w}-bit keys, pre-filled to load {prefill}; {n_req} requests ({total} operations) for the "
                       f"saturated and 50% runs, the first {n_req_other} for the other rates; sizes "
                       f"lognormal(median 4096, sigma 2) in 1..2^22, 70% find / 30% insert, pinned host buffers; "
-                      f"trace cut at load {stop_load}"),
+                      f"trace cut at load {stop_load}; staged servers admit by a staging ring sized from the free "
+                      f"device memory at start"),
            "requests": n_req, "operations": total}
     zero = np.zeros(n_req, dtype=np.uint64)
     res["saturated"] = run(zero, n_req, **cont)
