@@ -79,3 +79,38 @@ def test_noalloc_limits(gpu):
     with pytest.raises(cpht.CphtError) as e:
         ice.sorted_fop_noalloc(torch.zeros(8, dtype=torch.int32, device=gpu), out[:8])
     assert e.value.code == 7  # CPHT_E_STATE
+
+
+def test_noalloc_in_a_captured_graph(gpu):
+    """The call the entry point is for: captured in a HIP graph (nothing to
+    allocate during capture) and replayed three times.  Between the replays
+    an eager allocation-free call on another table overwrites the shared
+    scratch, so each replay must start from whatever the last call left
+    there; every replay gives the eager call's answers and key set."""
+    from tests.test_gpu_graphs import _capture
+
+    w = 37
+    t = _cuckoo(w, 18, 0x6D)
+    other = _cuckoo(w, 18, 0x6E)
+    n_before = 1 << 16
+    t.bulk_build(synth.distinct_keys(w, 0x6D, 0, n_before, device=gpu))
+    torch.cuda.synchronize()
+    img = t.export(0)
+    keys, _ = synth.find_or_put_batch(w, 0x6D, n_before, 1 << 16, 1 << 18, 5, device=gpu)
+    assert keys.numel() <= MAX_KEYS
+    out = torch.empty(keys.numel(), dtype=torch.uint8, device=gpu)
+    other_out = torch.empty(5000, dtype=torch.uint8, device=gpu)
+    t.sorted_fop_noalloc(keys, out)  # eager; also resolves the scratch address before capture
+    torch.cuda.synchronize()
+    want = out.clone()
+    want_set = check_table(t)
+    g = _capture(lambda s: t.sorted_fop_noalloc(keys, out, stream=s))
+    for rep in range(3):
+        other.sorted_fop_noalloc(keys[rep * 5000:(rep + 1) * 5000], other_out)
+        t.import_image(0, img)
+        out.fill_(0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert int((out != want).sum()) == 0, rep
+        assert np.array_equal(check_table(t), want_set), rep
