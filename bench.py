@@ -1238,8 +1238,10 @@ def serving_small(torch, cpht, synth, dev, n_burst=20000, burst_ops=64, reps=300
     (half finds of pre-filled keys, half inserts of fresh keys), staged,
     zero-copy and resident, beside a bare mixed launch + synchronise on device
     buffers; (2) a burst of n_burst requests of burst_ops operations in
-    separate pinned buffers submitted at once, per path.  Every answer of the
-    burst is checked (inserts of fresh keys PUT, finds of pre-filled keys 1)."""
+    separate pinned buffers submitted at once, per path; (3) 1024 requests of
+    2^16 operations back to back in one pinned buffer submitted at once, per
+    path.  Every answer of (2) and (3) is checked (inserts of fresh keys PUT,
+    of pre-filled keys FOUND, finds of pre-filled keys 1)."""
     import numpy as np
 
     w, L0, L1 = 40, 22, 19
@@ -1324,7 +1326,51 @@ def serving_small(torch, cpht, synth, dev, n_burst=20000, burst_ops=64, reps=300
         print(f"[bench] serving_small burst {name}: {dt * 1e3:.1f} ms", file=sys.stderr, flush=True)
         del t, reqs, outs
     out["burst"] = burst
-    out["check"] = "ok" if all(v["check"] == "ok" for v in burst.values()) else "FAILED"
+    # (3) saturated: n_sat requests of 2^16 operations back to back in one
+    # pinned buffer, submitted at once (each is one launch or one ring
+    # descriptor: max_batch_keys = 2^16).  Per request the first 256
+    # operations insert fresh keys (PUT), the rest alternate find-or-put and
+    # find of pre-filled keys (FOUND, 1).
+    n_sat, sat_ops, n_fresh = 1024, 1 << 16, 256
+    tot = n_sat * sat_ops
+    pos = torch.arange(tot, dtype=torch.int64, device=dev)
+    j = pos % sat_ops
+    is_fresh = j < n_fresh
+    idx = torch.where(is_fresh, n_pre + (pos // sat_ops) * n_fresh + j, (pos * 13) % n_pre)
+    ops_d = torch.where(is_fresh | (j % 2 == 0), 1, 0).to(torch.uint8)
+    want_d = torch.where(is_fresh, cpht.PUT, torch.where(j % 2 == 0, cpht.FOUND, 1)).to(torch.uint8)
+    keys_h = torch.empty(tot, dtype=torch.int64).pin_memory()
+    keys_h.copy_(synth.to_words(synth.feistel(w, KEY_SEED + 11, idx), w))
+    ops_h = torch.empty(tot, dtype=torch.uint8).pin_memory()
+    ops_h.copy_(ops_d)
+    want = want_d.cpu()
+    del pos, j, is_fresh, idx, ops_d, want_d
+    sat = {}
+    for name, kw in paths.items():
+        t = fresh_table()
+        res_h = torch.zeros(tot, dtype=torch.uint8).pin_memory()
+        srv = cpht.Server(t, **kw)
+        a = time.perf_counter()
+        tickets = [srv.submit(keys_h[i * sat_ops:(i + 1) * sat_ops], ops_h[i * sat_ops:(i + 1) * sat_ops],
+                              res_h[i * sat_ops:(i + 1) * sat_ops]) for i in range(n_sat)]
+        shown = a
+        for i, tk in enumerate(tickets):
+            srv.wait(tk)
+            if time.perf_counter() - shown > 10:
+                shown = time.perf_counter()
+                print(f"[bench] serving_small saturated {name}: {i + 1} of {n_sat} requests done",
+                      file=sys.stderr, flush=True)
+        dt = time.perf_counter() - a
+        st = srv.stats()
+        srv.stop()
+        ok = bool(torch.equal(res_h, want) and t.count()[0] == n_pre + n_sat * n_fresh)
+        sat[name] = {"ms": round(dt * 1e3, 2), "mops": round(tot / dt / 1e6, 1), "launches": st["launches"],
+                     "check": "ok" if ok else "FAILED"}
+        print(f"[bench] serving_small saturated {name}: {dt * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        del t, res_h
+    out["saturated_2e16_requests"] = sat
+    out["config"] += f"; saturated: {n_sat} requests of {sat_ops} operations back to back in one pinned buffer"
+    out["check"] = "ok" if all(v["check"] == "ok" for v in list(burst.values()) + list(sat.values())) else "FAILED"
     return out
 
 

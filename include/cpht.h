@@ -366,12 +366,14 @@ cpht_status_t cpht_multi_error(cpht_multi_t m, uint32_t* flags);
  * request descriptors from a ring of 1024 in pinned host memory (one per
  * request, or with coalesce = 1 one per run of queued requests that lie back
  * to back in all three buffers, up to max_batch_keys operations), cuts each
- * into chunks of 2048 operations that its blocks (two per compute unit, plus
- * one that watches the ring) take in order, and reports every completed
- * descriptor back through the ring; so up to 1024 descriptors are in flight
- * and overlap on the device, and an idle request costs no kernel launch.
- * A request larger than max_batch_keys is refused (CPHT_E_ARG) in this mode.  The kernel ends after idle_us without requests and is started
- * again by the next one.  While it runs it holds part of the device: work
+ * into chunks of 256 to 2048 operations (small while little work is in
+ * flight, so that a lone request is spread over many blocks) that its blocks
+ * (two per compute unit, plus one that watches the ring) take in order, and
+ * reports every completed descriptor back through the ring; so up to 1024
+ * descriptors are in flight and overlap on the device, and an idle request
+ * costs no kernel launch.  A request larger than max_batch_keys is refused
+ * (CPHT_E_ARG) in this mode.  The kernel ends after idle_us without requests
+ * and is started again by the next one.  While it runs it holds part of the device: work
  * that synchronises the whole device (hipDeviceSynchronize) waits until it
  * ends, so stop the server, or let it go idle, before such calls.
  * The server runs set operations (cpht_mixed): on a map table the values are

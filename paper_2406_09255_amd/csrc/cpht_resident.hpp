@@ -11,32 +11,41 @@
 //     descriptors and of the published chunk count, the chunk claim counter,
 //     per-slot completed-chunk counters and the stop epoch.
 //
-// Work is cut into chunks of CHUNK_KEYS consecutive operations of one
-// request; chunk ids are global and increase across requests (request seq
+// Work is cut into chunks of 2^chunk_log2 consecutive operations of one
+// request (256 to 2048, the host's choice per request: small chunks spread
+// a lone request over many blocks, large ones cut the per-chunk costs when
+// much work is in flight); chunk ids are global and increase across requests (request seq
 // covers [chunk_base, chunk_base + chunks)).  Block 0 is the leader: it
 // polls the host ring, copies new descriptors to device memory (up to 256 at
-// once, one per thread) and then publishes their chunks to the workers.  Every other block claims the next
-// published chunk with a CAS (never a chunk that is not published yet),
-// processes it with the iceberg mixed-batch body, and counts it done; the
-// block that completes a request's last chunk reports it to the host.
+// once, one per thread) and then publishes their chunks to the workers.
+// Every other block takes a ticket (the next chunk id, by an atomic add),
+// waits until that chunk is published, processes it with the iceberg
+// mixed-batch body, and counts it done; the block that completes a request's
+// last chunk reports it to the host.
 // Completed-chunk counters never reset: the host gives each descriptor the
 // running total its slot must reach (slot_target).
 //
 // Exit: the leader ends the loop (by writing the launch's epoch to
 // stop_epoch) when the host asks, or when neither a new request nor a chunk
 // claim has happened for idle_ticks of the device's constant-rate clock;
-// workers waiting for a chunk see the epoch and return, workers processing
-// a chunk finish it first.  So every wave of the launch ends within
+// workers waiting for an unpublished chunk see the epoch and return, workers
+// with a published chunk process it first.  So every wave of the launch ends within
 // idle_ticks of the last request (and, should the clock not advance, after
-// 2^26 polls without progress).  The host launches the loop again when it
-// publishes into a loop that has ended (the device counters carry over).
+// 2^26 polls without progress).  A waiting worker holds a ticket; at the end
+// it gives up a ticket whose chunk is not published, and the next launch's
+// leader restarts the ticket count at the last published chunk before any
+// worker takes one.  The host launches the loop again when it publishes into
+// a loop that has ended (the device counters carry over).
 #pragma once
+#include <cstddef>
+
 #include "cpht_iceberg.hpp"
 
 namespace cpht {
 
 constexpr uint32_t RING_SLOTS = 1024;      // descriptors in flight at most
-constexpr uint32_t CHUNK_KEYS = 2048;      // operations per chunk (8 x 256)
+constexpr uint32_t CHUNK_MIN_LOG2 = 8;     // operations per chunk: 256 ..
+constexpr uint32_t CHUNK_MAX_LOG2 = 11;    // .. 2048, chosen per request by the host
 
 struct RingDesc {
   const void* keys;      // device view of the request's pinned key words
@@ -46,6 +55,8 @@ struct RingDesc {
   uint64_t chunk_base;   // first global chunk id of the request
   uint64_t slot_target;  // completed chunks of this slot when the request is done
   uint64_t seq;          // the request's sequence number (its slot is seq % RING_SLOTS)
+  uint32_t chunk_log2;   // the request's chunks hold 2^chunk_log2 operations (the last one fewer)
+  uint32_t chunks;       // ceil(n / 2^chunk_log2)
 };
 
 struct RingCtl {
@@ -56,15 +67,21 @@ struct RingCtl {
   RingDesc desc[RING_SLOTS];
 };
 
+// Words the workers poll share one 128-byte line; the ticket counter, the
+// one word every chunk updates, has a line of its own.
 struct ResidentState {
-  uint64_t mirrored;        // descriptors the leader has copied (persists across launches)
   uint64_t pub_chunks;      // chunk ids [0, pub_chunks) are published to the workers
-  uint64_t next_chunk;      // next chunk id to claim
+  uint64_t mirrored;        // descriptors the leader has copied (persists across launches)
   uint32_t stop_epoch;      // epoch of the launch that has been told to end
-  uint32_t pad;
+  uint32_t run_epoch;       // epoch of the launch whose leader has set next_chunk up
+  uint64_t pad0[13];
+  uint64_t next_chunk;      // next chunk ticket
+  uint64_t pad1[15];
   uint64_t slot_done[RING_SLOTS];  // completed chunks per slot (running totals)
   RingDesc desc[RING_SLOTS];       // device copies of the descriptors
 };
+static_assert(offsetof(ResidentState, next_chunk) == 128 && offsetof(ResidentState, slot_done) == 256,
+              "hot words on their own lines");
 
 template <class KeyT, int S0, int S1, int B0, int B1, int G>
 __global__ __launch_bounds__(256) void iceberg_resident_kernel(TableK T, RingCtl* ctl, ResidentState* st,
@@ -84,8 +101,14 @@ __global__ __launch_bounds__(256) void iceberg_resident_kernel(TableK T, RingCtl
     uint64_t last_claim = 0, quiet = 0;
     long long t_active = 0;
     if (threadIdx.x == 0) {
+      // Tickets the previous launch handed out past its last published chunk
+      // were given up unused (see the workers' exit), so numbering restarts
+      // there; the workers take no ticket before run_epoch says so.
+      const uint64_t pc = __hip_atomic_load(&st->pub_chunks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&st->next_chunk, pc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&st->run_epoch, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       l_mirrored = st->mirrored;
-      last_claim = __hip_atomic_load(&st->next_chunk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      last_claim = pc;
       t_active = wall_clock64();
     }
 #pragma unroll 1
@@ -105,7 +128,7 @@ __global__ __launch_bounds__(256) void iceberg_resident_kernel(TableK T, RingCtl
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
         const RingDesc d = ctl->desc[q % RING_SLOTS];
         st->desc[q % RING_SLOTS] = d;
-        if (threadIdx.x == n_copy - 1) l_end = d.chunk_base + (d.n + CHUNK_KEYS - 1) / CHUNK_KEYS;
+        if (threadIdx.x == n_copy - 1) l_end = d.chunk_base + d.chunks;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this copy is visible device-wide
       }
       __syncthreads();
@@ -140,32 +163,46 @@ __global__ __launch_bounds__(256) void iceberg_resident_kernel(TableK T, RingCtl
   }
 
   uint64_t seq = 0;  // request of this block's last chunk (thread 0)
+  if (threadIdx.x == 0) {
+#pragma unroll 1
+    while (__hip_atomic_load(&st->run_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch)
+      __builtin_amdgcn_s_sleep(2);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
 #pragma unroll 1
   for (;;) {
     if (threadIdx.x == 0) {
       int cmd = 0;
+      // A ticket is the id of the chunk this block will process: one atomic
+      // add that always succeeds (a compare-and-swap on the shared counter
+      // lets one block in, per round trip, of all those trying).  The block
+      // then waits until its chunk is published, polling with relaxed loads
+      // (an acquire on every poll would invalidate this XCD's L2 under the
+      // working blocks) and acquiring once it is.  When the launch is told to
+      // end, a ticket that is published by then is still processed; one that
+      // is not is given up (the next launch restarts numbering at the last
+      // published chunk), so every published chunk is processed exactly once.
+      const uint64_t ticket = __hip_atomic_fetch_add(&st->next_chunk, 1ull, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll 1
-      // Poll with relaxed loads (an acquire on every poll would invalidate
-      // this XCD's L2 under the working blocks); acquire once a chunk is won.
       for (;;) {
-        const uint64_t pc = __hip_atomic_load(&st->pub_chunks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        uint64_t c = __hip_atomic_load(&st->next_chunk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (c < pc) {
-          if (__hip_atomic_compare_exchange_strong(&st->next_chunk, &c, c + 1, __ATOMIC_RELAXED,
-                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-            // pairs with the leader's release of pub_chunks: the descriptors
-            // covering chunk c (and the mirrored count) are visible
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            s_chunk = c;
-            cmd = 1;
-            break;
-          }
-          continue;  // another block took chunk c: look again
+        if (ticket < __hip_atomic_load(&st->pub_chunks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          cmd = 1;
+          break;
         }
-        if (__hip_atomic_load(&st->stop_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) break;
+        if (__hip_atomic_load(&st->stop_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) {
+          // the leader's last publication was released before its stop
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          if (ticket < __hip_atomic_load(&st->pub_chunks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) cmd = 1;
+          break;
+        }
         __builtin_amdgcn_s_sleep(10);
       }
       if (cmd == 1) {
+        // pairs with the leader's release of pub_chunks: the descriptors
+        // covering the chunk (and the mirrored count) are visible
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_chunk = ticket;
         // The request holding chunk s_chunk.  It was copied before its chunks
         // were published (the acquire above), it has not completed, and at
         // most RING_SLOTS requests are in flight, so it is one of the last
@@ -178,8 +215,7 @@ __global__ __launch_bounds__(256) void iceberg_resident_kernel(TableK T, RingCtl
 #pragma unroll 1
         for (; seq < m; ++seq) {
           const RingDesc& d = dd[seq % RING_SLOTS];
-          if (d.seq == seq && s_chunk >= d.chunk_base && s_chunk < d.chunk_base + (d.n + CHUNK_KEYS - 1) / CHUNK_KEYS)
-            break;
+          if (d.seq == seq && s_chunk >= d.chunk_base && s_chunk < d.chunk_base + d.chunks) break;
         }
         if (seq < m) {
           s_desc = dd[seq % RING_SLOTS];
@@ -197,8 +233,9 @@ __global__ __launch_bounds__(256) void iceberg_resident_kernel(TableK T, RingCtl
     // see the host's writes of this request's keys and opcodes (acquire, system scope)
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
     const RingDesc d = s_desc;
-    const uint64_t first = (s_chunk - d.chunk_base) * CHUNK_KEYS;
-    const uint64_t count = d.n - first < CHUNK_KEYS ? d.n - first : CHUNK_KEYS;
+    const uint64_t first = (s_chunk - d.chunk_base) << d.chunk_log2;
+    const uint64_t chunk_keys = 1ull << d.chunk_log2;
+    const uint64_t count = d.n - first < chunk_keys ? d.n - first : chunk_keys;
 #pragma unroll 1
     for (uint64_t o = 0; o < count; o += 256) {
       BatchK Bt;

@@ -111,6 +111,8 @@ struct cpht_server {
   uint64_t next_seq = 0;    // descriptors written
   uint64_t next_chunk = 0;  // chunk ids handed out
   std::vector<uint64_t> slot_total;                  // running chunk totals per ring slot
+  std::vector<uint64_t> slot_ops;                    // operations of the descriptor in each busy slot
+  uint64_t inflight_ops = 0;                         // operations of all descriptors in flight
   std::vector<std::vector<uint64_t>> slot_reqs;      // request ids in each busy slot
   std::vector<uint8_t> slot_busy;
   std::deque<uint64_t> rinflight;                    // descriptor seqs in flight, in publication order
@@ -276,6 +278,7 @@ void resident_dispatcher(cpht_server* s) {
       const uint64_t seq = *it;
       if (__atomic_load_n(&s->ctl->done[seq % RING_SLOTS], __ATOMIC_ACQUIRE) == seq + 1) {
         finished.push_back(seq);
+        s->inflight_ops -= s->slot_ops[seq % RING_SLOTS];
         it = s->rinflight.erase(it);
       } else {
         ++it;
@@ -335,6 +338,7 @@ void resident_dispatcher(cpht_server* s) {
         for (const Pending& pd : take)
           for (uint64_t id : s->slot_reqs[pd.slot]) s->reqs.find(id)->t_done = t;
         s->rinflight.clear();
+        s->inflight_ops = 0;
         take.clear();
         s->cv.notify_all();
         if (s->stopping) stop_now = true;
@@ -348,10 +352,18 @@ void resident_dispatcher(cpht_server* s) {
     if (stop_now) break;
     // 3. write the descriptors and publish them (the device reads them only
     //    after the release store of the count)
+    // chunk size: the work in flight spread over the workers, within the
+    // 256..2048-operation range (one lone request is served by many blocks at
+    // once; a full ring pays the per-chunk costs on large chunks)
+    for (const Pending& pd : take) s->inflight_ops += pd.total;
+    const uint64_t per_worker = (s->inflight_ops + s->workers - 1) / s->workers;
+    uint32_t lg = CHUNK_MIN_LOG2;
+    while (lg < CHUNK_MAX_LOG2 && (1ull << lg) < per_worker) ++lg;
     for (const Pending& pd : take) {
       const uint64_t seq = s->next_seq++;
-      const uint64_t chunks = (pd.total + CHUNK_KEYS - 1) / CHUNK_KEYS;
+      const uint64_t chunks = (pd.total + (1ull << lg) - 1) >> lg;
       s->slot_total[pd.slot] += chunks;
+      s->slot_ops[pd.slot] = pd.total;
       RingDesc& d = s->ctl->desc[pd.slot];
       d.keys = pd.first.dkeys;
       d.ops = pd.first.dops;
@@ -360,6 +372,8 @@ void resident_dispatcher(cpht_server* s) {
       d.chunk_base = s->next_chunk;
       d.slot_target = s->slot_total[pd.slot];
       d.seq = seq;
+      d.chunk_log2 = lg;
+      d.chunks = (uint32_t)chunks;
       s->next_chunk += chunks;
       s->rinflight.push_back(seq);
     }
@@ -555,6 +569,7 @@ hipError_t resident_setup(cpht_server* s) {
   s->idle_ticks = (uint64_t)s->cfg.idle_us * (uint64_t)(rate_khz > 0 ? rate_khz : 100000) / 1000ull;
   s->workers = (uint32_t)(cus > 0 ? 2 * cus : 512);
   s->slot_total.assign(RING_SLOTS, 0);
+  s->slot_ops.assign(RING_SLOTS, 0);
   s->slot_reqs.assign(RING_SLOTS, {});
   s->slot_busy.assign(RING_SLOTS, 0);
   return hipSuccess;
