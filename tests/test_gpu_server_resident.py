@@ -182,3 +182,38 @@ def test_resident_configuration_checks(gpu):
     with pytest.raises(cpht.CphtError) as e:  # tables beyond the covered size
         cpht.Server(big, zero_copy=1, resident=1, max_batch_keys=1 << 16)
     assert e.value.code == 3
+
+
+def test_resident_chunk_sizes_follow_the_work_in_flight(gpu):
+    """The loop cuts each request into chunks sized from the operations in
+    flight: a lone request of 2^17 operations (small chunks, spread over the
+    workers), then 64 such requests at once (large chunks), then a lone one
+    again.  Per request the first 256 operations insert fresh keys (PUT), the
+    rest alternate find-or-put and find of pre-filled keys (FOUND, 1)."""
+    pre, size, n_fresh = 300000, 1 << 17, 256
+    t = _table(39)
+    S0 = _prefill(t, gpu, pre)
+    srv = cpht.Server(t, zero_copy=1, resident=1, coalesce=0, max_batch_keys=size)
+    j = torch.arange(size, dtype=torch.int64)
+    first = j < n_fresh
+    ops = torch.where(first | (j % 2 == 0), 1, 0).to(torch.uint8)
+    want = torch.where(first, cpht.PUT, torch.where(j % 2 == 0, cpht.FOUND, 1)).to(torch.uint8)
+    fresh_next, fresh_all = pre, []
+    for phase, n_req in enumerate((1, 64, 1)):
+        reqs, outs = [], []
+        for i in range(n_req):
+            idx = torch.where(first, fresh_next + j, (j * 7 + 13 * (i + 64 * phase)) % pre)
+            fresh_all.append(idx[:n_fresh])
+            fresh_next += n_fresh
+            kb = synth.to_words(synth.feistel(W, 77, idx), W).pin_memory()
+            reqs.append((kb, ops.pin_memory()))
+            outs.append(torch.zeros(size, dtype=torch.uint8).pin_memory())
+        tickets = [srv.submit(k, o, r) for (k, o), r in zip(reqs, outs)]
+        for tk in tickets:
+            srv.wait(tk)
+        for i, r in enumerate(outs):
+            bad = torch.nonzero(r != want).flatten()
+            assert bad.numel() == 0, f"phase {phase}, request {i}: {bad.numel()} wrong answers, first at {bad[:5]}"
+    srv.stop()
+    fresh_keys = host_u64(synth.feistel(W, 77, torch.cat(fresh_all)))
+    assert np.array_equal(check_table(t), np.union1d(S0, fresh_keys))
