@@ -601,6 +601,10 @@ def cpu_full(torch, synth, dev, sweep=(0.5, 0.7, 0.8, 0.9, 0.95), batch=1 << 20)
                   flush=True)
     occ, capo = ice.occupied(), ice.capacity()
     del mk, mo, ice
+    many = _cpu_many_tables_sample(torch, synth, dev)
+    print(f"[bench] cpu_full many tables: {many}", file=sys.stderr, flush=True)
+    srv = _cpu_serving_sample(torch, synth, dev)
+    print(f"[bench] cpu_full serving: {srv}", file=sys.stderr, flush=True)
     return {
         "kind": "oracle", "cores": 1, "host_threads_available": os.cpu_count(), "host_cpu": _host_cpu(),
         "cuckoo_load_sweep": rows,
@@ -612,8 +616,95 @@ def cpu_full(torch, synth, dev, sweep=(0.5, 0.7, 0.8, 0.9, 0.95), batch=1 << 20)
                                    "count_matches": occ == n_fresh},
         "iceberg_shape": (f"iceberg 2^{L0} + 2^{L1} slots, B0=32 x 16-bit, B1=16 x 32-bit, {w}-bit keys; "
                           f"{nb} mixed batches of {batch} ops (the GPU run's batches), load 0 -> {LOAD}"),
+        "many_tables_sample": many,
+        "serving_sample": srv,
         "seconds": round(time.perf_counter() - t_all, 1),
     }
+
+
+def _cpu_many_tables_sample(torch, synth, dev, n_tables=4096, n_sample=256, lo=10, hi=20, load=0.85):
+    """The sequential oracle on the first n_sample tables of the many-table
+    workload (the same size draw, 2^e + 2^(e-3) slots, 32-bit keys; buckets
+    of 32 x 32-bit primary and 16 x 32-bit secondary slots): each filled to
+    the load with distinct keys, then queried with twice its capacity in finds
+    (half hits on its own keys, half misses)."""
+    import numpy as np
+
+    import oracle
+
+    w = 32
+    e_t = (synth.uniform_below(0xE5, n_tables, hi - lo + 1, dev) + lo).cpu().tolist()[:n_sample]
+    rng = np.random.default_rng(0xAB)
+    base, ins_s, find_s, n_ins, n_find, hits = 0, 0.0, 0.0, 0, 0, 0
+    for i, e in enumerate(e_t):
+        cap = (1 << e) + (1 << (e - 3))
+        n, nq = int(cap * load), 2 * cap
+        keys = synth.distinct_keys(w, KEY_SEED + 9, base, n).numpy().astype(np.uint64)
+        miss = synth.distinct_keys(w, KEY_SEED + 9, (1 << 31) + base, nq).numpy().astype(np.uint64)
+        base += n
+        hit = rng.random(nq) < 0.5
+        q = np.where(hit, keys[rng.integers(0, n, nq)], miss)
+        tab = oracle.Table(oracle.ICEBERG, w, e, 32, 32, log2_slots1=e - 3, B1=16, s1=32, seed=7000 + i)
+        a = time.perf_counter()
+        out = tab.insert(keys)
+        b = time.perf_counter()
+        f = tab.find(q)
+        c = time.perf_counter()
+        assert (out == oracle.PUT).all() and np.array_equal(f.astype(bool), hit), f"oracle table {i}"
+        ins_s, find_s = ins_s + (b - a), find_s + (c - b)
+        n_ins, n_find, hits = n_ins + n, n_find + nq, hits + int(hit.sum())
+        del tab
+    return {"tables": n_sample, "of": n_tables, "inserts": n_ins, "finds": n_find,
+            "insert_mops": round(n_ins / ins_s / 1e6, 3), "find_mops": round(n_find / find_s / 1e6, 3),
+            "ops_mops": round((n_ins + n_find) / (ins_s + find_s) / 1e6, 3), "seconds": round(ins_s + find_s, 1)}
+
+
+def _cpu_serving_sample(torch, synth, dev, log2_slots0=28, prefill=0.5, ops_max=1 << 25, seed=3):
+    """The sequential oracle on the serving workload at 1/16 of the table
+    (2^28 + 2^25 slots, 16/32-bit; the GPU table has 2^32 + 2^29 with 40-bit
+    keys, and the key width shrinks with the table, to 36 bits, so that the
+    stored remainders keep their width and fit the 16-bit slots):
+    pre-filled to load 0.5, then the first requests of the same trace
+    (lognormal sizes, 70 % finds at half hits, 30 % inserts of fresh keys)
+    up to ops_max operations, applied in arrival order.  Every answer is
+    checked."""
+    import numpy as np
+
+    import oracle
+
+    L0, L1 = log2_slots0, log2_slots0 - 3
+    w = 40 - (32 - L0)
+    cap = (1 << L0) + (1 << L1)
+    n_pre = int(prefill * cap)
+    tab = oracle.Table(oracle.ICEBERG, w, L0, 32, 16, log2_slots1=L1, B1=16, s1=32, seed=23)
+    pre_s = 0.0
+    for a in range(0, n_pre, 1 << 24):
+        k = synth.distinct_keys(w, KEY_SEED + 7, a, min(1 << 24, n_pre - a), device=dev).cpu().numpy()
+        t0 = time.perf_counter()
+        out = tab.insert(k.astype(np.uint64))
+        pre_s += time.perf_counter() - t0
+        assert (out == oracle.PUT).all()
+    r = np.random.default_rng(seed)
+    sizes = np.clip(np.round(np.exp(r.normal(np.log(4096), 2.0, 100000))), 1, 1 << 22).astype(np.int64)
+    n_req = int(np.searchsorted(np.cumsum(sizes), ops_max, side="right"))
+    total = int(sizes[:n_req].sum())
+    is_ins = synth.uniform_below(0x31, total, 10, dev) < 3
+    is_hit = synth.uniform_below(0x32, total, 2, dev) == 1
+    fresh_idx = n_pre + torch.cumsum(is_ins.to(torch.int64), 0)
+    hit_idx = synth.uniform_below(0x33, total, 1 << 30, dev) * n_pre >> 30
+    miss_idx = (1 << (w - 1)) + torch.arange(total, device=dev)
+    idx = torch.where(is_ins, fresh_idx, torch.where(is_hit, hit_idx, miss_idx))
+    keys = synth.feistel(w, KEY_SEED + 7, idx).cpu().numpy().astype(np.uint64)
+    ops = is_ins.to(torch.uint8).cpu().numpy()
+    want = np.where(ops == 1, oracle.PUT, is_hit.cpu().numpy().astype(np.uint8)).astype(np.uint8)
+    del is_ins, is_hit, fresh_idx, hit_idx, miss_idx, idx
+    t0 = time.perf_counter()
+    got = tab.mixed(keys, ops)
+    run_s = time.perf_counter() - t0
+    assert np.array_equal(got, want), "oracle serving sample"
+    return {"table": f"2^{L0} + 2^{L1} slots (16/32-bit), {w}-bit keys, pre-filled to load {prefill}",
+            "prefill_inserts": n_pre, "prefill_mops": round(n_pre / pre_s / 1e6, 3), "requests": n_req,
+            "operations": total, "mops": round(total / run_s / 1e6, 3), "seconds": round(pre_s + run_s, 1)}
 
 
 def small_cuckoo(torch, cpht, synth, dev, reps=20):
