@@ -240,8 +240,8 @@ cpht_status_t cpht_sorted_fop_workspace(cpht_table_t t, uint64_t n, uint64_t* by
  * find-or-put as cpht_sorted_fop, with the same answers, but its scratch is a
  * fixed 40 MiB array of device memory that the library holds on each GPU it
  * runs on until the process ends (its address is looked up once per device,
- * on the first call there).  The call allocates nothing and takes no
- * workspace.  n <= 2^20 keys (CPHT_E_ARG above that; CPHT_E_STATE on an
+ * when the first cuckoo table on that device is created, so the call makes no
+ * runtime lookup).  The call allocates nothing and takes no workspace.  n <= 2^20 keys (CPHT_E_ARG above that; CPHT_E_STATE on an
  * iceberg table).  All calls on one GPU share that GPU's array: calls that
  * overlap on one GPU (other streams, other threads, other tables) race and
  * give undefined answers; order them on one stream or synchronise between

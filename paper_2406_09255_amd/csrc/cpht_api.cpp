@@ -293,6 +293,13 @@ cpht_status_t cpht_create(const cpht_config_t* cfg, cpht_table_t* out) {
     K.vals[x] = t->vals[x];
   }
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&t->d_counter), sizeof(unsigned long long));
+  if (e == hipSuccess && t->ck) {
+    // set-up of the allocation-free sorted find-or-put on this device: its
+    // scratch array's address is looked up here, once per device, so that
+    // the call itself (possibly under graph capture) makes no runtime lookup
+    void* scratch_addr = nullptr;
+    e = sorted_fop_scratch(t->device, &scratch_addr);
+  }
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     for (int x = 0; x < 4; ++x)

@@ -100,7 +100,7 @@ def test_noalloc_in_a_captured_graph(gpu):
     assert keys.numel() <= MAX_KEYS
     out = torch.empty(keys.numel(), dtype=torch.uint8, device=gpu)
     other_out = torch.empty(5000, dtype=torch.uint8, device=gpu)
-    t.sorted_fop_noalloc(keys, out)  # eager; also resolves the scratch address before capture
+    t.sorted_fop_noalloc(keys, out)  # eager: the answers and key set every replay must give
     torch.cuda.synchronize()
     want = out.clone()
     want_set = check_table(t)
