@@ -5,8 +5,9 @@
 // Shared state:
 //   RingCtl (pinned host memory, mapped for the device, coherent): the host
 //     writes request descriptors and then advances `published`; the device
-//     writes done[slot] = seq + 1 when request seq has completed.  `stop`
-//     asks the loop to end.
+//     writes done[slot] = seq + 1 when request seq has completed, and the
+//     launch's epoch into `ended` when its leader ends it.  `stop` asks the
+//     loop to end.
 //   ResidentState (device memory): the leader's copy of the published
 //     descriptors and of the published chunk count, the chunk claim counter,
 //     per-slot completed-chunk counters and the stop epoch.
@@ -63,6 +64,8 @@ struct RingCtl {
   uint64_t published;  // descriptors published by the host (descriptor seq sits at slot seq % RING_SLOTS)
   uint32_t stop;       // host: 1 = end the loop
   uint32_t fault;      // device: 1 = a block found no request for its chunk (the ring protocol was broken)
+  uint32_t ended;      // device: epoch of the last launch whose leader has ended it
+  uint32_t pad;
   uint64_t done[RING_SLOTS];  // device: seq + 1 once request seq has completed
   RingDesc desc[RING_SLOTS];
 };
@@ -153,6 +156,8 @@ __global__ __launch_bounds__(256) void iceberg_resident_kernel(TableK T, RingCtl
         }
         if (l_exit || (uint64_t)(now - t_active) > idle_ticks || ++quiet > (1ull << 26)) {
           __hip_atomic_store(&st->stop_epoch, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          // tells the host that publications from now on need a new launch
+          __hip_atomic_store(&ctl->ended, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
           l_exit = 1;
         }
       }

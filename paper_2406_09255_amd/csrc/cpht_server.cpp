@@ -381,14 +381,16 @@ void resident_dispatcher(cpht_server* s) {
     if (published) __atomic_store_n(&s->ctl->published, s->next_seq, __ATOMIC_RELEASE);
     // 4. the loop must be running while requests are in flight: it ends by
     //    itself when idle, possibly just before a publication it did not see
+    //    (the loop's leader writes its epoch into the ring when it ends; a new
+    //    launch queues behind the old one's last blocks on the same stream;
+    //    the stream itself is queried only now and then, for device errors)
     if (!s->rinflight.empty() && !s->error) {
       const uint64_t t = now_ns();
-      bool relaunch = !s->loop_launched;
-      if (!relaunch && (published || t - s->last_query_ns > 50000)) {
+      bool relaunch = !s->loop_launched || __atomic_load_n(&s->ctl->ended, __ATOMIC_ACQUIRE) == s->epoch;
+      if (t - s->last_query_ns > 1000000) {
         s->last_query_ns = t;
         const hipError_t q = hipStreamQuery(s->rstream);
-        if (q == hipSuccess) relaunch = true;
-        else if (q != hipErrorNotReady) s->error = 1;
+        if (q != hipSuccess && q != hipErrorNotReady) s->error = 1;
       }
       if (relaunch && !s->error) {
         const hipError_t e = launch_loop(s);

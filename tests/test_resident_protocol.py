@@ -15,7 +15,9 @@ the chunk's descriptor among the last RING mirrored, processes it and counts
 it on its slot; the block that reaches the slot's running total reports the
 request.  The host publishes descriptors into free slots with chunk sizes
 taken from the work in flight and relaunches the loop when requests are in
-flight and the previous launch has ended.
+flight and the leader of the current launch has written that it ended; a
+launch starts once the previous one's blocks have all finished (one
+stream).
 
 Checked: every published chunk is processed exactly once, by one block;
 every request completes, with its done word set only after all its chunks
@@ -55,6 +57,7 @@ class Shared:
         # observations
         self.processed = {}      # chunk id -> count
         self.fault = False
+        self.ended = 0           # epoch of the last launch whose leader ended it
 
 
 def leader(S, epoch, bug):
@@ -96,6 +99,8 @@ def leader(S, epoch, bug):
         quiet = 0 if progress else quiet + 1
         if stop or quiet > IDLE_ITERS:
             S.stop_epoch = epoch
+            yield
+            S.ended = epoch
             yield
             return
 
@@ -168,13 +173,17 @@ def run_model(seed, n_req=40, workers=3, bug=None):
     next_chunk = 0
     inflight_ops = 0
     completed = []
-    launches = []      # lists of live generators, one list per launch
+    launches = []      # lists of generators (None once finished), one list per launch, in stream order
+    running = 0        # launches before this one have finished; it runs once launched
     epoch = 0
     steps = 0
     while True:
         steps += 1
         assert steps < 200000, "no progress"
-        live = [g for g in (launches[-1] if launches else []) if g is not None]
+        # launches run one after another on the stream
+        while running < len(launches) and all(g is None for g in launches[running]):
+            running += 1
+        live = [g for g in launches[running] if g is not None] if running < len(launches) else []
         # the host is one more actor
         actors = ["host"] + list(range(len(live)))
         a = rng.choice(actors)
@@ -209,11 +218,13 @@ def run_model(seed, n_req=40, workers=3, bug=None):
                 inflight[q] = (slot, ops)
             if take:
                 S.published = next_seq
-            # relaunch when requests are in flight and the loop has ended
-            if inflight and not live:
+            # relaunch when requests are in flight and the current launch's
+            # leader has ended it (its last blocks may still run: the new
+            # launch queues behind them)
+            if inflight and (epoch == 0 or S.ended == epoch):
                 epoch += 1
                 launches.append([leader(S, epoch, bug)] + [worker(S, epoch, bug) for _ in range(workers)])
-            if next_req == n_req and not inflight and not live:
+            if next_req == n_req and not inflight and not live and running == len(launches):
                 break
             continue
         g = live[a]
@@ -223,7 +234,7 @@ def run_model(seed, n_req=40, workers=3, bug=None):
             try:
                 next(g)
             except StopIteration:
-                cur = launches[-1]
+                cur = launches[running]
                 cur[cur.index(g)] = None
                 break
         if S.fault:
