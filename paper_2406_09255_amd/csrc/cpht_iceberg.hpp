@@ -65,11 +65,14 @@ __device__ __forceinline__ uint32_t alloc_slab(const Level3K& L3) {
   return id <= L3.nslabs ? id : 0u;
 }
 
-// Keys whose buckets one sub-tile loads together (buffers within 32
-// registers per lane).
-template <int G, int W>
+// Keys whose buckets one sub-tile loads together, within a budget of REGS
+// registers per lane for the buffers.  Level 1 gets 32.  Level 2 gets 16:
+// only keys whose primary bucket is full reach it, yet its buffers (two
+// buckets per key) set the kernel's peak register count, and with 32 they
+// held the 16/32-bit, 32-slot kernels at 4 waves per SIMD instead of 5.
+template <int G, int W, int REGS = 32>
 struct IceDepth {
-  static constexpr int D = G * W <= 32 ? G : (32 / W > 0 ? 32 / W : 1);
+  static constexpr int D = G * W <= REGS ? G : (REGS / W > 0 ? REGS / W : 1);
   static_assert(G % D == 0, "prefetch depth must divide the sub-tile");
 };
 
@@ -104,7 +107,7 @@ __device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, 
   using KM0 = KnownMask<B0>;
   using KM1 = KnownMask<B1>;
   constexpr int W0 = Sh::W0, W1 = Sh::W1, PER0 = Sh::PER0, PER1 = Sh::PER1, HG = Sh::HG;
-  constexpr int D0 = IceDepth<G, W0>::D, D1 = IceDepth<G, W1>::D;
+  constexpr int D0 = IceDepth<G, W0>::D, D1 = IceDepth<G, W1, 16>::D;
   const SubTile<G> st;
   const LevelK& L0 = T.lv[0];
   const LevelK& L1 = T.lv[1];
