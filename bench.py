@@ -62,7 +62,7 @@ KERNEL_SOURCES = ("cpht_device.hpp", "cpht_cuckoo.hpp", "cpht_registry.hpp", "in
 # Measured HBM bytes per operation (read + written, same calibration) of the
 # iceberg kernels at the iceberg_static shape, profiles/iceberg_hbm_bytes.md;
 # valid for the iceberg sources they were taken with.
-ICE_TRAFFIC = {"src_sha": "4f0db539c0954be3", "insert_16_32": 222.9, "find_16_32": 214.3,
+ICE_TRAFFIC = {"src_sha": "e487985929bbc784", "insert_16_32": 222.9, "find_16_32": 214.3,
                "insert_64_64": 352.6, "find_64_64": 344.0}
 ICE_SOURCES = ("cpht_device.hpp", "cpht_iceberg.hpp", "cpht_registry.hpp", "inst_iceberg_u64.hip")
 

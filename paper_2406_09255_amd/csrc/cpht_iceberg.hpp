@@ -66,10 +66,11 @@ __device__ __forceinline__ uint32_t alloc_slab(const Level3K& L3) {
 }
 
 // Keys whose buckets one sub-tile loads together, within a budget of REGS
-// registers per lane for the buffers.  Level 1 gets 32.  Level 2 gets 16:
-// only keys whose primary bucket is full reach it, yet its buffers (two
-// buckets per key) set the kernel's peak register count, and with 32 they
-// held the 16/32-bit, 32-slot kernels at 4 waves per SIMD instead of 5.
+// registers per lane for the buffers.  Level 1 gets 32.  Levels 2 and 3 get
+// 16: only keys whose primary bucket is full reach them, yet their buffers
+// set the kernel's peak register count; with 32 they held the 16/32-bit,
+// 32-slot kernels at 4 waves per SIMD instead of 5 (3 instead of 4 with the
+// third level).
 template <int G, int W, int REGS = 32>
 struct IceDepth {
   static constexpr int D = G * W <= REGS ? G : (REGS / W > 0 ? REGS / W : 1);
@@ -360,7 +361,7 @@ __device__ __forceinline__ void iceberg_body(const TableK& T, const BatchK& Bt, 
           else if (ins) link = true;
           else { result = 0; stage = 0; }
         }
-        constexpr int D3 = IceDepth<G, W3>::D;
+        constexpr int D3 = IceDepth<G, W3, 16>::D;
 #pragma unroll 1
         for (int t0 = 0; t0 < G; t0 += D3) {
           uint32_t buf[D3][W3];
