@@ -30,6 +30,7 @@ without re-reading the published count) must each be caught.
 from __future__ import annotations
 
 import random
+import sys
 
 import pytest
 
@@ -250,6 +251,21 @@ def test_resident_protocol_exactly_once(seed):
     assert sorted(S.processed) == list(range(n_chunks)), "every published chunk is processed"
     assert all(v == 1 for v in S.processed.values()), "no chunk is processed twice"
     assert n_launch >= 1
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_resident_protocol_larger_ring(seed, monkeypatch):
+    """The same checks with a 16-slot ring, copies of up to 8 descriptors per
+    leader pass, 200 requests and up to 8 workers."""
+    mod = sys.modules[__name__]
+    monkeypatch.setattr(mod, "RING", 16)
+    monkeypatch.setattr(mod, "COPY_MAX", 8)
+    assert Shared().done == [0] * 16
+    S, n_chunks, completed, _ = run_model(seed, n_req=200, workers=1 + seed % 8)
+    assert not S.fault
+    assert sorted(completed) == list(range(200))
+    assert sorted(S.processed) == list(range(n_chunks))
+    assert all(v == 1 for v in S.processed.values())
 
 
 def _fails(bug, seeds=range(200)):
