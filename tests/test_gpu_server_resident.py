@@ -217,3 +217,30 @@ def test_resident_chunk_sizes_follow_the_work_in_flight(gpu):
     srv.stop()
     fresh_keys = host_u64(synth.feistel(W, 77, torch.cat(fresh_all)))
     assert np.array_equal(check_table(t), np.union1d(S0, fresh_keys))
+
+
+def test_resident_many_idle_exits_between_bursts(gpu):
+    """Forty bursts of three requests with a pause longer than idle_us after
+    each: every burst finds the loop ended, so each launch starts by taking
+    back the tickets the previous one gave up; every answer and the final key
+    set follow the set semantics."""
+    pre = 8000
+    reqs = _packed(_requests(120, pre, 16, pre))
+    t = _table(40)
+    S0 = _prefill(t, gpu, pre)
+    srv = cpht.Server(t, zero_copy=1, resident=1, idle_us=100, max_batch_keys=1 << 16)
+    outs = []
+    for b in range(0, len(reqs), 3):
+        burst = reqs[b:b + 3]
+        res = [torch.zeros(k.numel(), dtype=torch.uint8).pin_memory() for k, _ in burst]
+        tickets = [srv.submit(k, o, r) for (k, o), r in zip(burst, res)]
+        for tk in tickets:
+            srv.wait(tk)
+        outs.extend(r.numpy().copy() for r in res)
+        time.sleep(0.003)  # well past idle_us: the loop ends before the next burst
+    st = srv.stats()
+    srv.stop()
+    assert st["requests_done"] == len(reqs)
+    assert st["launches"] >= 20  # most bursts started a new launch
+    S = _check_stream(reqs, outs, S0)
+    assert np.array_equal(check_table(t), S)
